@@ -1,0 +1,116 @@
+"""Brute-force references used to pin the CPU oracle (dense NumPy, tiny inputs)."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def patterns(n, rowptr, col):
+    return [tuple(col[rowptr[i]:rowptr[i + 1]].tolist()) for i in range(n)]
+
+
+def identical_pattern_partition(n, rowptr, col):
+    """Groups of rows with the same nonempty pattern, ordered by smallest member; empty rows alone."""
+    first = {}
+    group = np.empty(n, dtype=np.int64)
+    for i, pat in enumerate(patterns(n, rowptr, col)):
+        if len(pat) == 0:
+            group[i] = i
+            continue
+        group[i] = first.setdefault(pat, i)
+    return _partition_from_group(group)
+
+
+def _partition_from_group(group):
+    n = len(group)
+    seeds = sorted(set(group.tolist()))
+    perm, bptr = [], [0]
+    for s in seeds:
+        members = [i for i in range(n) if group[i] == s]
+        perm.extend(members)
+        bptr.append(len(perm))
+    return np.array(perm, dtype=np.int32), np.array(bptr, dtype=np.int32)
+
+
+def angle_partition_bruteforce(n, rowptr, col, tau):
+    """Sequential seed loop with cosines from the dense pattern product C C^T (float, with sqrt).
+
+    Returns (perm, bptr, closest_margin) where closest_margin is the smallest |cos - tau|
+    seen, so callers can make sure no decision was borderline."""
+    c = np.zeros((n, n))
+    for i in range(n):
+        c[i, col[rowptr[i]:rowptr[i + 1]]] = 1.0
+    g = c @ c.T
+    ln = np.diag(g).copy()
+    group = -np.ones(n, dtype=np.int64)
+    margin = np.inf
+    for i in range(n):
+        if group[i] != -1:
+            continue
+        group[i] = i
+        if ln[i] == 0:
+            continue
+        for j in range(i + 1, n):
+            if group[j] != -1 or ln[j] == 0:
+                continue
+            cos = g[i, j] / np.sqrt(ln[i] * ln[j])
+            margin = min(margin, abs(cos - tau))
+            if cos >= tau:
+                group[j] = i
+    perm, bptr = _partition_from_group(group)
+    return perm, bptr, margin
+
+
+def greedy_is_bruteforce(adj_sets):
+    """Natural-order greedy independent set on an undirected graph given as neighbour sets."""
+    p = len(adj_sets)
+    marked = np.zeros(p, bool)
+    out = []
+    for v in range(p):
+        if marked[v]:
+            continue
+        out.append(v)
+        marked[v] = True
+        for u in adj_sets[v]:
+            marked[u] = True
+    return np.array(out, dtype=np.int32)
+
+
+def quotient_adjacency(bm):
+    """Neighbour sets of the quotient graph of A + A^T from a block matrix (self loops removed)."""
+    adj = [set() for _ in range(bm.p)]
+    for i in range(bm.p):
+        for k in range(bm.rowptr[i], bm.rowptr[i + 1]):
+            j = int(bm.colidx[k])
+            if j != i:
+                adj[i].add(j)
+                adj[j].add(i)
+    return adj
+
+
+def block_sumsq_ratio(b, t):
+    m, n = b.shape
+    return float(np.sum(b * b)) / (t * m * n) ** 2
+
+
+def node_rows_reversed(s, mode="reverse"):
+    """The system with the rows of every node block reversed (or cyclically shifted by one).
+
+    The block pattern is unchanged, but each diagonal block's dominant entries move off
+    its diagonal, so partial pivoting has to swap rows in every pivot block; the cyclic
+    shift makes successive swaps share rows, so their order matters."""
+    from paper_1508_02219_amd.synth import System
+    ell = np.asarray(s.node_ell, dtype=np.int64)
+    start = np.concatenate([[0], np.cumsum(ell)])
+    newrow = np.empty(s.n, dtype=np.int64)
+    for u in range(len(ell)):
+        a, b = start[u], start[u + 1]
+        if mode == "reverse":
+            newrow[a:b] = np.arange(b - 1, a - 1, -1)
+        else:
+            newrow[a:b] = a + (np.arange(b - a) - 1) % (b - a)
+    order = np.argsort(newrow)  # new row r takes old row order[r]
+    counts = np.diff(s.rowptr)[order]
+    rowptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    col = np.concatenate([s.col[s.rowptr[o]:s.rowptr[o + 1]] for o in order]).astype(np.int32)
+    val = np.concatenate([s.val[s.rowptr[o]:s.rowptr[o + 1]] for o in order])
+    return System(s.n, rowptr, col, val, s.b[order], s.node_ell, name=s.name + "-rev")

@@ -1,0 +1,502 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: brute force on tiny
+inputs, closed forms, exact algebraic identities at zero dropping, or library routines
+for the special cases that reduce to them.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from paper_1508_02219_amd import synth
+from tests import oracle_helpers as H
+
+
+def _oracle(O, s, tau, levels, droptol, drop_schur=1):
+    perm, bptr = O.compress(s.n, s.rowptr, s.col, tau)
+    return O.Oracle(s.n, s.rowptr, s.col, s.val, perm, bptr, levels, droptol, drop_schur), perm, bptr
+
+
+def _split(bm, is_list):
+    """Scalar index sets of independent-set blocks and of the rest (both ascending)."""
+    isb = set(int(i) for i in is_list)
+    rows_is = np.concatenate([np.arange(bm.rb[i], bm.rb[i + 1]) for i in sorted(isb)] or [np.zeros(0, int)])
+    rest = [i for i in range(bm.p) if i not in isb]
+    rows_rest = np.concatenate([np.arange(bm.rb[i], bm.rb[i + 1]) for i in rest] or [np.zeros(0, int)])
+    return rows_is.astype(int), rows_rest.astype(int)
+
+
+def _block_lu_parts(dm):
+    """From an exported pivot-block matrix: dense block diagonals P^T L and U."""
+    n = dm.rb[-1]
+    PtL = np.zeros((n, n))
+    Uu = np.zeros((n, n))
+    for i in range(dm.p):
+        a, b = dm.rb[i], dm.rb[i + 1]
+        m = b - a
+        lu = dm.block(i)
+        Lm = np.tril(lu, -1) + np.eye(m)
+        Um = np.triu(lu)
+        P = np.eye(m)
+        for k in range(m):
+            pk = dm.piv[a + k]
+            P[[k, pk]] = P[[pk, k]]
+        PtL[a:b, a:b] = P.T @ Lm
+        Uu[a:b, a:b] = Um
+    return PtL, Uu
+
+
+# --------------------------------------------------------------------------------------
+# Compression (Sec. 2.1)
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_tau_one_gives_identical_pattern_classes(orc, seed):
+    s = synth.random_pattern_matrix(90, 0.06, twins=30, seed=seed)
+    perm, bptr = orc.compress(s.n, s.rowptr, s.col, 1.0)
+    p2, b2 = H.identical_pattern_partition(s.n, s.rowptr, s.col)
+    np.testing.assert_array_equal(perm, p2)
+    np.testing.assert_array_equal(bptr, b2)
+
+
+def test_empty_rows_stay_singletons(orc):
+    n = 6
+    rowptr = np.array([0, 0, 2, 2, 4, 4, 4], dtype=np.int64)  # rows 0, 2, 4, 5 empty
+    col = np.array([1, 3, 1, 3], dtype=np.int32)
+    perm, bptr = orc.compress(n, rowptr, col, 0.5)
+    np.testing.assert_array_equal(perm, [0, 1, 3, 2, 4, 5])
+    np.testing.assert_array_equal(bptr, [0, 1, 3, 4, 5, 6])
+
+
+@pytest.mark.parametrize("tau", [0.3183, 0.5772, 0.7071, 0.9133])
+@pytest.mark.parametrize("seed", [5, 6])
+def test_angle_compression_matches_bruteforce(orc, tau, seed):
+    s = synth.random_pattern_matrix(140, 0.05, twins=25, seed=seed)
+    perm, bptr = orc.compress(s.n, s.rowptr, s.col, tau)
+    p2, b2, margin = H.angle_partition_bruteforce(s.n, s.rowptr, s.col, tau)
+    assert margin > 1e-9
+    np.testing.assert_array_equal(perm, p2)
+    np.testing.assert_array_equal(bptr, b2)
+
+
+def test_angle_compression_on_perturbed_stencil_matches_bruteforce(orc):
+    s = synth.grid_system(3, 3, 3, ell=5, stencil="14rand", perturb=0.10, seed=7)
+    for tau in (0.61, 0.8, 0.93):
+        perm, bptr = orc.compress(s.n, s.rowptr, s.col, tau)
+        p2, b2, margin = H.angle_partition_bruteforce(s.n, s.rowptr, s.col, tau)
+        assert margin > 1e-9
+        np.testing.assert_array_equal(perm, p2)
+        np.testing.assert_array_equal(bptr, b2)
+
+
+def test_perfect_blocks_recovered(orc):
+    s = synth.grid_system(4, 3, 3, ell=4, stencil="7pt", seed=3)
+    perm, bptr = orc.compress(s.n, s.rowptr, s.col, 1.0)
+    np.testing.assert_array_equal(perm, np.arange(s.n))
+    np.testing.assert_array_equal(bptr, np.arange(0, s.n + 1, 4))
+    o = orc.Oracle(s.n, s.rowptr, s.col, s.val, perm, bptr, 0, 0.0)
+    a = o.matrix(orc.LAST)
+    cells = sum((a.rb[i + 1] - a.rb[i]) * (a.cb[a.colidx[k] + 1] - a.cb[a.colidx[k]])
+                for i in range(a.p) for k in range(a.rowptr[i], a.rowptr[i + 1]))
+    assert cells == s.nnz  # average block density 1
+
+
+def test_twin_nodes_merge(orc):
+    # two mutually coupled nodes are indistinguishable: one block of 2*ell rows
+    s = synth.grid_system(1, 1, 2, ell=3, stencil="7pt", seed=1)
+    perm, bptr = orc.compress(s.n, s.rowptr, s.col, 1.0)
+    np.testing.assert_array_equal(bptr, [0, 6])
+
+
+def test_tau_one_relabel_invariant(orc):
+    s = synth.random_pattern_matrix(80, 0.07, twins=20, seed=11)
+    rng = np.random.default_rng(0)
+    q = rng.permutation(s.n)  # new index k holds old row q[k]
+    a = s.dense()
+    pat = a != 0
+    ap = a[np.ix_(q, q)]
+    pp = pat[np.ix_(q, q)]
+    rows, cols = np.nonzero(pp)
+    rowptr = np.zeros(s.n + 1, np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    perm1, bptr1 = orc.compress(s.n, s.rowptr, s.col, 1.0)
+    perm2, bptr2 = orc.compress(s.n, rowptr, cols.astype(np.int32), 1.0)
+    g1 = {frozenset(perm1[bptr1[i]:bptr1[i + 1]].tolist()) for i in range(len(bptr1) - 1)}
+    g2 = {frozenset(q[perm2[bptr2[i]:bptr2[i + 1]]].tolist()) for i in range(len(bptr2) - 1)}
+    assert g1 == g2
+    del ap
+
+
+def test_compress_rejects_bad_tau(orc):
+    s = synth.random_pattern_matrix(10, 0.2, seed=1)
+    for tau in (0.0, -0.5, 1.5, float("nan")):
+        with pytest.raises(ValueError):
+            orc.compress(s.n, s.rowptr, s.col, tau)
+
+
+# --------------------------------------------------------------------------------------
+# Independent set (Sec. 2, Sec. 3 Step 3)
+# --------------------------------------------------------------------------------------
+def test_independent_set_checkerboard_closed_form(orc):
+    s = synth.config_system(1)
+    o, perm, bptr = _oracle(orc, s, 1.0, 1, 1e-3)
+    nodes = np.arange(1000)
+    x, y, z = nodes % 10, (nodes // 10) % 10, nodes // 100
+    expect = nodes[(x + y + z) % 2 == 0]
+    np.testing.assert_array_equal(o.level_is(0), expect)
+    assert len(expect) == 500
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_independent_set_matches_bruteforce_all_levels(orc, seed):
+    s = synth.random_pattern_matrix(150, 0.03, twins=20, seed=seed + 20, diag=6.0)
+    o, perm, bptr = _oracle(orc, s, 0.6, 3, 1e-3)
+    assert o.status == 0
+    for lvl in range(o.nlevels):
+        a = o.matrix(orc.AS, lvl)
+        adj = H.quotient_adjacency(a)
+        is_list = o.level_is(lvl)
+        np.testing.assert_array_equal(is_list, H.greedy_is_bruteforce(adj))
+        iset = set(is_list.tolist())
+        for v in iset:  # independent
+            assert not (adj[v] & iset)
+        for v in range(a.p):  # maximal
+            assert v in iset or (adj[v] & iset)
+
+
+# --------------------------------------------------------------------------------------
+# Scaling (Sec. 3 Step 2)
+# --------------------------------------------------------------------------------------
+def test_scaling_unit_maxima(orc):
+    s = synth.grid_system(3, 3, 4, ell=3, stencil="14rand", perturb=0.1, seed=4)
+    o, perm, bptr = _oracle(orc, s, 0.8, 2, 1e-3)
+    for lvl in range(o.nlevels):
+        a = o.matrix(orc.A, lvl).dense()
+        asd = o.matrix(orc.AS, lvl).dense()
+        s1, s2 = o.level_scaling(lvl)
+        np.testing.assert_array_equal(s1, 1.0 / np.abs(a).max(axis=1))
+        cmax = np.abs(asd).max(axis=0)
+        rmax = np.abs(asd).max(axis=1)
+        assert np.all(np.abs(cmax - 1.0) <= 4e-16)
+        assert np.all(rmax <= 1.0 + 4e-16)
+        np.testing.assert_allclose(asd, (s1[:, None] * a) * s2[None, :], rtol=0, atol=0)
+
+
+# --------------------------------------------------------------------------------------
+# Partial block factorization (Sec. 3 Step 4, Eq. vbarms, Eq. schurcomp)
+# --------------------------------------------------------------------------------------
+def test_pivot_blocks_match_lapack_getrf(orc):
+    s = synth.grid_system(4, 4, 3, ell=5, stencil="14rand", seed=9)
+    o, perm, bptr = _oracle(orc, s, 1.0, 1, 1e-3)
+    asd = o.matrix(orc.AS, 0)
+    dm = o.matrix(orc.D, 0)
+    for t, i in enumerate(o.level_is(0)):
+        k = [kk for kk in range(asd.rowptr[i], asd.rowptr[i + 1]) if asd.colidx[kk] == i][0]
+        lu, piv = sla.lu_factor(asd.block(k))
+        np.testing.assert_array_equal(dm.piv[dm.rb[t]:dm.rb[t + 1]], piv)
+        np.testing.assert_allclose(dm.block(t), lu, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("system", ["grid", "rand"])
+def test_zero_drop_schur_and_factorization_identity(orc, system):
+    if system == "grid":
+        s = synth.grid_system(4, 3, 3, ell=4, stencil="14rand", perturb=0.1, seed=12)
+        tau = 0.8
+    else:
+        s = synth.random_pattern_matrix(120, 0.04, twins=30, seed=13, diag=8.0)
+        tau = 0.55
+    o, perm, bptr = _oracle(orc, s, tau, 1, 0.0)
+    assert o.status == 0
+    As = o.matrix(orc.AS, 0)
+    a = As.dense()
+    ri, rr = _split(As, o.level_is(0))
+    D, F, E, Cm = a[np.ix_(ri, ri)], a[np.ix_(ri, rr)], a[np.ix_(rr, ri)], a[np.ix_(rr, rr)]
+    S_exact = Cm - E @ np.linalg.solve(D, F)
+    S = o.matrix(orc.LAST).dense()
+    scale = np.abs(S_exact).max()
+    assert np.abs(S - S_exact).max() <= 1e-12 * scale
+    # Eq. vbarms: [D F; E C] = [P^T L 0; W I] [U G; 0 S]
+    PtL, Uu = _block_lu_parts(o.matrix(orc.D, 0))
+    G = o.matrix(orc.G, 0).dense()
+    Wm = o.matrix(orc.W, 0).dense()
+    ni, nr = len(ri), len(rr)
+    left = np.block([[PtL, np.zeros((ni, nr))], [Wm, np.eye(nr)]])
+    right = np.block([[Uu, G], [np.zeros((nr, ni)), S]])
+    full = np.block([[D, F], [E, Cm]])
+    assert np.abs(left @ right - full).max() <= 1e-12 * np.abs(full).max()
+
+
+def test_dropping_matches_dense_bruteforce(orc):
+    s = synth.grid_system(4, 4, 4, ell=3, stencil="14rand", perturb=0.1, seed=21)
+    t = 0.012
+    o, perm, bptr = _oracle(orc, s, 0.8, 1, [t, 0.0])
+    assert o.status == 0
+    As = o.matrix(orc.AS, 0)
+    is_list = o.level_is(0)
+    isset = set(is_list.tolist())
+    rest = [i for i in range(As.p) if i not in isset]
+    num = {int(b): k for k, b in enumerate(is_list)}
+    num.update({b: k for k, b in enumerate(rest)})
+    dm = o.matrix(orc.D, 0)
+    PtL, Uu = _block_lu_parts(dm)
+    margins = []
+    # expected G, W blocks (dense per block), applying the drop rule
+    Gx, Wx = {}, {}
+    nF = nE = 0
+    for i in range(As.p):
+        for k in range(As.rowptr[i], As.rowptr[i + 1]):
+            j = int(As.colidx[k])
+            blk = As.block(k)
+            if i in isset and j not in isset:
+                nF += 1
+                a, b = dm.rb[num[i]], dm.rb[num[i] + 1]
+                val = np.linalg.solve(PtL[a:b, a:b], blk)
+                r = H.block_sumsq_ratio(val, t)
+                margins.append(abs(r - 1))
+                if r >= 1:
+                    Gx[(num[i], num[j])] = val
+            if i not in isset and j in isset:
+                nE += 1
+                a, b = dm.rb[num[j]], dm.rb[num[j] + 1]
+                val = np.linalg.solve(Uu[a:b, a:b].T, blk.T).T
+                r = H.block_sumsq_ratio(val, t)
+                margins.append(abs(r - 1))
+                if r >= 1:
+                    Wx[(num[i], num[j])] = val
+    assert min(margins) > 1e-9
+    G, Wm = o.matrix(orc.G, 0), o.matrix(orc.W, 0)
+
+    def blocks(bm):
+        return {(i, int(bm.colidx[k])): bm.block(k) for i in range(bm.p)
+                for k in range(bm.rowptr[i], bm.rowptr[i + 1])}
+
+    gb, wb = blocks(G), blocks(Wm)
+    assert set(gb) == set(Gx) and set(wb) == set(Wx)
+    assert 0 < len(gb) < nF and 0 < len(wb) < nE  # the threshold both keeps and drops
+    for key in Gx:
+        np.testing.assert_allclose(gb[key], Gx[key], rtol=1e-12, atol=1e-14)
+    for key in Wx:
+        np.testing.assert_allclose(wb[key], Wx[key], rtol=1e-12, atol=1e-14)
+    # Schur with dropped W, G blocks, then off-diagonal dropping
+    nr = len(rest)
+    rsz = [As.rb[b + 1] - As.rb[b] for b in rest]
+    Sx = {}
+    n_before = 0
+    for jn, J in enumerate(rest):
+        acc = {}
+        for k in range(As.rowptr[J], As.rowptr[J + 1]):
+            K = int(As.colidx[k])
+            if K not in isset:
+                acc[num[K]] = As.block(k).copy()
+        for (wj, wi), wv in sorted(Wx.items()):
+            if wj != jn:
+                continue
+            for (gi, gk), gv in sorted(Gx.items()):
+                if gi != wi:
+                    continue
+                acc.setdefault(gk, np.zeros((rsz[jn], rsz[gk])))
+                acc[gk] = acc[gk] - wv @ gv
+        n_before += len(acc)
+        for K, v in acc.items():
+            r = H.block_sumsq_ratio(v, t)
+            if K == jn or r >= 1:
+                Sx[(jn, K)] = v
+            if K != jn:
+                margins.append(abs(r - 1))
+    assert min(margins) > 1e-9
+    sb = blocks(o.matrix(orc.LAST))
+    assert set(sb) == set(Sx)
+    assert nr < len(sb) < n_before
+    for key in Sx:
+        np.testing.assert_allclose(sb[key], Sx[key], rtol=1e-11, atol=1e-13)
+
+
+def test_no_schur_drop_mode_keeps_all_blocks(orc):
+    s = synth.grid_system(4, 4, 3, ell=3, stencil="14rand", perturb=0.1, seed=22)
+    o1, _, _ = _oracle(orc, s, 0.8, 1, [0.05, 0.0], drop_schur=1)
+    o0, _, _ = _oracle(orc, s, 0.8, 1, [0.05, 0.0], drop_schur=0)
+    a1, a0 = o1.matrix(orc.LAST), o0.matrix(orc.LAST)
+    assert a0.nb > a1.nb
+    d0 = a0.dense()
+    d1 = a1.dense()
+    kept = d1 != 0
+    np.testing.assert_array_equal(d0[kept], d1[kept])
+
+
+# --------------------------------------------------------------------------------------
+# Last level block ILUT (Sec. 3, Alg. 3)
+# --------------------------------------------------------------------------------------
+def test_last_level_ilut_exact_without_dropping(orc):
+    s = synth.grid_system(4, 4, 3, ell=3, stencil="14rand", perturb=0.1, seed=31)
+    o, _, _ = _oracle(orc, s, 0.8, 1, 0.0)
+    A = o.matrix(orc.LAST).dense()
+    Lm = o.matrix(orc.L).dense() + np.eye(A.shape[0])
+    Um = o.matrix(orc.U).dense()
+    PtL, Uu = _block_lu_parts(o.matrix(orc.DL))
+    Um = Um + PtL @ Uu
+    assert np.abs(Lm @ Um - A).max() <= 1e-12 * np.abs(A).max()
+    # block lower / upper structure
+    Lb, Ub = o.matrix(orc.L), o.matrix(orc.U)
+    for i in range(Lb.p):
+        assert all(Lb.colidx[Lb.rowptr[i]:Lb.rowptr[i + 1]] < i)
+        assert all(Ub.colidx[Ub.rowptr[i]:Ub.rowptr[i + 1]] > i)
+
+
+def test_last_level_huge_threshold_is_block_jacobi(orc):
+    s = synth.grid_system(3, 3, 3, ell=4, stencil="14rand", seed=32)
+    o, _, _ = _oracle(orc, s, 1.0, 0, 1e9)
+    assert o.matrix(orc.L).nb == 0 and o.matrix(orc.U).nb == 0
+    A = o.matrix(orc.LAST)
+    dl = o.matrix(orc.DL)
+    for i in range(A.p):
+        k = [kk for kk in range(A.rowptr[i], A.rowptr[i + 1]) if A.colidx[kk] == i][0]
+        lu, piv = sla.lu_factor(A.block(k))
+        np.testing.assert_allclose(dl.block(i), lu, rtol=1e-13, atol=1e-15)
+
+
+# --------------------------------------------------------------------------------------
+# Preconditioner application (Alg. 2)
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("levels", [0, 1, 2, 3])
+def test_apply_is_exact_inverse_without_dropping(orc, levels):
+    s = synth.grid_system(4, 3, 3, ell=3, stencil="14rand", perturb=0.1, seed=41)
+    o, _, _ = _oracle(orc, s, 0.8, levels, 0.0)
+    assert o.status == 0
+    rng = np.random.default_rng(levels)
+    x = rng.standard_normal(s.n)
+    y = o.apply(x)
+    ye = np.linalg.solve(s.dense(), x)
+    assert np.abs(y - ye).max() <= 1e-10 * np.abs(ye).max()
+
+
+def test_apply_with_dropping_is_linear_and_approximate(orc):
+    s = synth.grid_system(5, 4, 4, ell=5, stencil="14rand", perturb=0.1, seed=42)
+    o, _, _ = _oracle(orc, s, 0.8, 2, 1e-2)
+    rng = np.random.default_rng(1)
+    x1, x2 = rng.standard_normal(s.n), rng.standard_normal(s.n)
+    y = o.apply(2.0 * x1 - 3.0 * x2)
+    np.testing.assert_allclose(y, 2.0 * o.apply(x1) - 3.0 * o.apply(x2), rtol=1e-10, atol=1e-12)
+    a = s.dense()
+    err = np.linalg.norm(a @ o.apply(x1) - x1) / np.linalg.norm(x1)
+    assert 1e-10 < err < 1.0
+
+
+# --------------------------------------------------------------------------------------
+# FGMRES (Sec. 4.1)
+# --------------------------------------------------------------------------------------
+def test_fgmres_unpreconditioned_history_is_krylov_least_squares(orc):
+    rng = np.random.default_rng(3)
+    n = 40
+    a = np.eye(n) * 2.0 + rng.standard_normal((n, n)) / np.sqrt(n)
+    b = rng.standard_normal(n)
+    rows, cols = np.nonzero(a)
+    rowptr = np.zeros(n + 1, np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    x, st, its, rel, hist = orc.fgmres(n, rowptr, cols.astype(np.int32), a[rows, cols], b, None,
+                                       tol=1e-15, restart=40, maxit=12)
+    assert its == 12
+    K = np.empty((n, 12))
+    v = b.copy()
+    for k in range(12):
+        K[:, k] = v
+        v = a @ v
+    for k in range(1, 13):
+        Q, _ = np.linalg.qr(K[:, :k])
+        yk, *_ = np.linalg.lstsq(a @ Q, b, rcond=None)
+        best = np.linalg.norm(b - a @ Q @ yk) / np.linalg.norm(b)
+        assert abs(hist[k] - best) <= 1e-9 * max(best, 1e-12) + 1e-13
+    assert np.all(np.diff(hist) <= 1e-15)
+
+
+def test_fgmres_exact_preconditioner_converges_in_one_iteration(orc):
+    s = synth.grid_system(4, 3, 3, ell=3, stencil="14rand", perturb=0.1, seed=51)
+    o, _, _ = _oracle(orc, s, 0.8, 2, 0.0)
+    x, st, its, rel, hist = orc.fgmres(s.n, s.rowptr, s.col, s.val, s.b, o, tol=1e-8, restart=30)
+    assert st == 0 and its == 1 and rel <= 1e-8
+
+
+def test_fgmres_true_residual_and_restarts(orc):
+    s = synth.grid_system(6, 6, 6, ell=5, stencil="14rand", perturb=0.1, seed=52)
+    o, _, _ = _oracle(orc, s, 0.8, 2, 5e-2)
+    x, st, its, rel, hist = orc.fgmres(s.n, s.rowptr, s.col, s.val, s.b, o, tol=1e-8, restart=5)
+    assert st == 0
+    r = s.b - s.dense() @ x
+    assert np.linalg.norm(r) / np.linalg.norm(s.b) <= 1e-8
+    assert abs(np.linalg.norm(r) / np.linalg.norm(s.b) - rel) <= 1e-12
+    assert its > 5  # needed at least one restart
+    x, st, its, rel, hist = orc.fgmres(s.n, s.rowptr, s.col, s.val, s.b, o, tol=1e-8, restart=5, maxit=2)
+    assert st == orc.NOT_CONVERGED and its == 2
+
+
+def test_singular_pivot_block_reported(orc):
+    s = synth.grid_system(3, 3, 2, ell=3, stencil="7pt", seed=61)
+    val = s.val.copy()
+    # zero out every entry of node 0's diagonal block -> its pivot block is singular
+    for r in range(3):
+        for k in range(s.rowptr[r], s.rowptr[r + 1]):
+            if s.col[k] < 3:
+                val[k] = 0.0
+    perm, bptr = orc.compress(s.n, s.rowptr, s.col, 1.0)
+    o = orc.Oracle(s.n, s.rowptr, s.col, val, perm, bptr, 1, 1e-3)
+    assert o.status == orc.ERR_SINGULAR and o.err_level == 0 and o.err_block == 0
+
+
+# --------------------------------------------------------------------------------------
+# Inputs that force row pivoting inside every pivot block
+# --------------------------------------------------------------------------------------
+def _pivoting_system(mode="reverse"):
+    return H.node_rows_reversed(synth.grid_system(4, 3, 3, ell=4, stencil="14rand", seed=71), mode)
+
+
+def test_pivoting_pivot_blocks_match_lapack_getrf(orc):
+    s = _pivoting_system()
+    o, _, _ = _oracle(orc, s, 1.0, 1, 0.0)
+    asd = o.matrix(orc.AS, 0)
+    dm = o.matrix(orc.D, 0)
+    swaps = 0
+    for t, i in enumerate(o.level_is(0)):
+        k = [kk for kk in range(asd.rowptr[i], asd.rowptr[i + 1]) if asd.colidx[kk] == i][0]
+        lu, piv = sla.lu_factor(asd.block(k))
+        got = dm.piv[dm.rb[t]:dm.rb[t + 1]]
+        np.testing.assert_array_equal(got, piv)
+        swaps += int(np.sum(got != np.arange(len(got))))
+        np.testing.assert_allclose(dm.block(t), lu, rtol=1e-13, atol=1e-15)
+    assert swaps > 0
+
+
+@pytest.mark.parametrize("mode", ["reverse", "shift"])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_pivoting_apply_is_exact_inverse(orc, levels, mode):
+    s = _pivoting_system(mode)
+    o, _, _ = _oracle(orc, s, 1.0, levels, 0.0)
+    assert o.status == 0
+    x = np.random.default_rng(7).standard_normal(s.n)
+    ye = np.linalg.solve(s.dense(), x)
+    y = o.apply(x)
+    assert np.abs(y - ye).max() <= 1e-10 * np.abs(ye).max()
+
+
+@pytest.mark.parametrize("mode", ["reverse", "shift"])
+def test_pivoting_zero_drop_identity_and_ilut(orc, mode):
+    s = _pivoting_system(mode)
+    o, _, _ = _oracle(orc, s, 1.0, 1, 0.0)
+    As = o.matrix(orc.AS, 0)
+    a = As.dense()
+    ri, rr = _split(As, o.level_is(0))
+    D, F, E, Cm = a[np.ix_(ri, ri)], a[np.ix_(ri, rr)], a[np.ix_(rr, ri)], a[np.ix_(rr, rr)]
+    PtL, Uu = _block_lu_parts(o.matrix(orc.D, 0))
+    G = o.matrix(orc.G, 0).dense()
+    Wm = o.matrix(orc.W, 0).dense()
+    np.testing.assert_allclose(PtL @ G, F, atol=1e-12 * np.abs(F).max())
+    np.testing.assert_allclose(Wm @ Uu, E, atol=1e-12 * np.abs(E).max())
+    S = o.matrix(orc.LAST).dense()
+    S_exact = Cm - E @ np.linalg.solve(D, F)
+    assert np.abs(S - S_exact).max() <= 1e-12 * np.abs(S_exact).max()
+    Lm = o.matrix(orc.L).dense() + np.eye(S.shape[0])
+    PtL2, Uu2 = _block_lu_parts(o.matrix(orc.DL))
+    Um = o.matrix(orc.U).dense() + PtL2 @ Uu2
+    assert np.abs(Lm @ Um - S).max() <= 1e-12 * np.abs(S).max()
+    # the multipliers are L_ik = w_k D_k^{-1}: check one against a dense solve
+    Lb = o.matrix(orc.L)
+    assert Lb.nb > 0

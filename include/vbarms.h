@@ -1,0 +1,206 @@
+/*
+ * vbarms.h -- C ABI of the MI355X VBARMS library (libvbarms.so).
+ *
+ * VBARMS is the variable-block algebraic recursive multilevel ILU preconditioner of
+ * Carpentieri, Liao, Sosonkina and Bonfiglioli, "Using the VBARMS method in parallel
+ * computing" (arXiv:1508.02219).  This library runs the method's hot path on one
+ * gfx950 GPU:
+ *
+ *   vbarms_compress  angle-based compression of a CSR matrix into variable blocks
+ *                    (Sec. 2.1) and the permuted variable-block matrix (Eq. blockperm)
+ *   vbarms_factor    per level: scaling (Sec. 3 Step 2), block independent set on the
+ *                    quotient graph (Step 3), partial block factorization with
+ *                    threshold dropping (Step 4, Eq. vbarms, Eq. schurl); block ILUT on
+ *                    the last Schur complement (Sec. 3, Alg. 3)
+ *   vbarms_apply     the multilevel solve (Alg. 2) with the inverse permutations
+ *   vbarms_spmv      y = A x with the compressed matrix
+ *   vbarms_solve     right-preconditioned FGMRES(m) (Sec. 4.1)
+ *
+ * Conventions
+ *  - Every pointer documented as DEVICE must point to memory allocated on the handle's
+ *    device (hipMalloc or a torch CUDA tensor); HOST pointers are ordinary host memory.
+ *  - The caller owns every buffer passed in; the library never keeps a caller pointer
+ *    after the call returns (vbarms_compress copies what it needs).
+ *  - The handle owns the compressed matrix, all factors and all workspace until
+ *    vbarms_destroy.
+ *  - Work is enqueued on the stream given to vbarms_create.  Calls that return host
+ *    data (statistics, solver info, exports) synchronize that stream.
+ *  - Indices: rows, columns and blocks are int32; offsets into value arrays are int64.
+ *  - Every call returns VBARMS_OK (0) on success, VBARMS_NOT_CONVERGED (1) when a solve
+ *    ran to maxit without meeting tol (its result and info are still valid), or a
+ *    negative error code; vbarms_last_error() then describes the failure.  No C++
+ *    exception crosses this interface.
+ *  - A handle is not thread safe; different handles may be used concurrently.
+ */
+#ifndef VBARMS_H
+#define VBARMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VBARMS_OK 0
+#define VBARMS_NOT_CONVERGED 1
+#define VBARMS_ERR_ARG (-1)      /* invalid argument (sizes, tau outside (0,1], NULL) */
+#define VBARMS_ERR_HIP (-2)      /* a HIP runtime call failed */
+#define VBARMS_ERR_OOM (-3)      /* device allocation or a documented capacity exceeded */
+#define VBARMS_ERR_SINGULAR (-4) /* a pivot block is exactly singular (GEPP met a zero column) */
+#define VBARMS_ERR_NAN (-5)      /* NaN or Inf in the input matrix or right-hand side */
+#define VBARMS_ERR_STATE (-6)    /* call out of order (e.g. apply before factor) */
+
+#define VBARMS_MAX_BLOCK 32      /* largest variable block the kernels accept */
+#define VBARMS_MAX_LEVELS 16
+
+/* precision of the factors (the Krylov solver is always FP64) */
+#define VBARMS_F64 0
+#define VBARMS_F32 1
+
+typedef struct vbarms_ctx *vbarms_t;
+
+/* Square sparse matrix in CSR form.  DEVICE pointers: rowptr[n+1] (int64, rowptr[0] = 0),
+ * col[nnz] (int32, sorted ascending within each row, no duplicates), val[nnz] (FP64).
+ * The stored entries define the pattern (explicit zeros count as entries). */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
+} vbarms_csr;
+
+/* Compression statistics (Sec. 2): av_bd = nnz(A) / (entries of all nonzero blocks),
+ * av_bs = n / number of diagonal blocks. */
+typedef struct {
+    int32_t nblocks;   /* p, number of diagonal blocks (supernodes) */
+    int32_t max_block; /* largest block size */
+    int64_t nnz_blocks;/* number of nonzero blocks of the permuted matrix */
+    double av_bd;
+    double av_bs;
+} vbarms_cstats;
+
+/* Factorization parameters.  droptol[l] is the threshold t of level l (Sec. 3: a block B
+ * of size m x n is dropped when ||B||_F / (m n) < t); droptol[levels] is used by the
+ * last-level block ILUT.  drop_schur = 1 also drops small off-diagonal blocks of every
+ * Schur complement; 0 keeps them all (the paper's wording for intermediate levels). */
+typedef struct {
+    int32_t levels;                        /* number of Schur reductions (0 = block ILUT only) */
+    double droptol[VBARMS_MAX_LEVELS + 1];
+    int32_t drop_schur;
+    int32_t precision;                     /* VBARMS_F64 or VBARMS_F32 */
+} vbarms_fparams;
+
+typedef struct {
+    int32_t iters;       /* Arnoldi steps taken */
+    int32_t restarts;    /* completed restart cycles */
+    double true_relres;  /* ||b - A x|| / ||b|| of the returned x */
+    int32_t status;      /* same as the return value */
+} vbarms_sinfo;
+
+/* Phase timings of the last calls, milliseconds of device time on the handle's stream. */
+typedef struct {
+    double compress_ms, factor_ms, solve_ms;
+    double factor_level_ms[VBARMS_MAX_LEVELS];
+    double ilut_ms;
+    int32_t levels;          /* levels actually factored */
+    int32_t last_p;          /* supernodes handed to the last-level ILUT */
+    int64_t factor_values;   /* stored values of all factors (Mem = factor_values / nnz(A)) */
+    int64_t nnz;             /* nnz(A) */
+} vbarms_fstats;
+
+/* Creates a handle bound to the current HIP device and to `hip_stream` (a hipStream_t,
+ * NULL = the null stream).  Returns VBARMS_ERR_HIP if no device is present. */
+int vbarms_create(vbarms_t *h, void *hip_stream);
+int vbarms_destroy(vbarms_t h);
+/* Text of the last error on this handle (never NULL; "" after success). */
+const char *vbarms_last_error(vbarms_t h);
+
+/* Angle-based compression (Sec. 2.1): rows i < j share a block when the cosine of their
+ * 0/1 patterns is >= tau, comparing each row with the seed of its group only; seeds are
+ * taken in ascending row order and empty rows stay alone.  tau must be in (0, 1]; tau = 1
+ * groups exactly the rows with identical patterns.  Builds the permuted variable-block
+ * matrix inside the handle (Eq. blockperm; every block row carries its diagonal block).
+ * Outputs (DEVICE, may be NULL): perm[n] (new position -> original row), bptr[p+1]
+ * (scalar offsets of the blocks; caller provides n+1 entries).  st (HOST, may be NULL)
+ * receives the statistics.  Errors: ARG (bad tau / n), NAN, OOM (a block row with more
+ * than 2048 distinct block columns, or a block larger than VBARMS_MAX_BLOCK). */
+int vbarms_compress(vbarms_t h, const vbarms_csr *A, double tau,
+                    int32_t *perm, int32_t *bptr, vbarms_cstats *st);
+
+/* Uses a given block partition instead of computing one: perm[n], bptr[p+1] are DEVICE
+ * arrays with the same meaning as the outputs of vbarms_compress. */
+int vbarms_set_partition(vbarms_t h, const vbarms_csr *A, const int32_t *perm,
+                         const int32_t *bptr, int32_t p, vbarms_cstats *st);
+
+/* Multilevel factorization of the compressed matrix (Sec. 3, Steps 2-4 repeated, then
+ * block ILUT).  Stops early when an independent set is empty or the Schur complement has
+ * no rows.  Errors: STATE (no compressed matrix), SINGULAR (exactly singular pivot
+ * block; see vbarms_error_location), OOM. */
+int vbarms_factor(vbarms_t h, const vbarms_fparams *p);
+
+/* Level and block of the last SINGULAR error (level == levels means the last level). */
+int vbarms_error_location(vbarms_t h, int32_t *level, int32_t *block);
+
+/* y = M^{-1} x with the multilevel factors (Alg. 2), DEVICE vectors of length n in the
+ * original numbering.  x and y must not overlap.  Errors: STATE before factor. */
+int vbarms_apply(vbarms_t h, const double *x, double *y);
+
+/* y = A x with the compressed matrix (original numbering, DEVICE vectors). */
+int vbarms_spmv(vbarms_t h, const double *x, double *y);
+
+/* Solves A x = b by FGMRES(restart) preconditioned on the right with M (Sec. 4.1).
+ * b, x: DEVICE vectors of length n in the original numbering; x holds the initial guess
+ * on entry (zeros for x0 = 0) and the solution on exit.  Stops when the true relative
+ * residual ||b - A x|| / ||b|| <= tol, checked at every restart, or after maxit Arnoldi
+ * steps (returns VBARMS_NOT_CONVERGED).  info (HOST, may be NULL) is filled either way. */
+int vbarms_solve(vbarms_t h, const double *b, double *x, double tol, int32_t restart,
+                 int32_t maxit, vbarms_sinfo *info);
+
+/* Timings and sizes of the last compress / factor / solve on this handle (HOST). */
+int vbarms_get_stats(vbarms_t h, vbarms_fstats *st);
+
+/* ---------------------------------------------------------------------------------- */
+/* Inspection of the factors (for verification and analysis).  All outputs are HOST.  */
+/* ---------------------------------------------------------------------------------- */
+/* Matrices that can be exported (block sparse row, dense row-major blocks):
+ *   VBARMS_M_A     A_l as handed to level l (A_0 = permuted input matrix)
+ *   VBARMS_M_AS    S1 A_l S2 (scaled, level numbering)
+ *   VBARMS_M_G     L^{-1} P F of level l (IS rows, remaining columns)
+ *   VBARMS_M_W     E U^{-1} of level l (remaining rows, IS columns)
+ *   VBARMS_M_D     LU factors of the IS pivot blocks of level l (block diagonal, pivots)
+ *   VBARMS_M_LAST  matrix handed to the last-level ILUT
+ *   VBARMS_M_L     last-level unit block lower factor (strictly lower blocks)
+ *   VBARMS_M_U     last-level block upper factor without its diagonal blocks
+ *   VBARMS_M_DL    LU factors of the last-level pivot blocks (block diagonal, pivots) */
+#define VBARMS_M_A 0
+#define VBARMS_M_AS 1
+#define VBARMS_M_G 2
+#define VBARMS_M_W 3
+#define VBARMS_M_D 4
+#define VBARMS_M_LAST 5
+#define VBARMS_M_L 6
+#define VBARMS_M_U 7
+#define VBARMS_M_DL 8
+
+/* levels actually factored */
+int vbarms_num_levels(vbarms_t h, int32_t *levels);
+/* info[4] = {p, n, nis, n_is} of level l */
+int vbarms_level_info(vbarms_t h, int32_t level, int32_t *info);
+/* independent-set supernodes of level l, ascending (length nis) */
+int vbarms_level_is(vbarms_t h, int32_t level, int32_t *is_list);
+/* scaling vectors S1, S2 of level l (length n of the level) */
+int vbarms_level_scaling(vbarms_t h, int32_t level, double *s1, double *s2);
+/* dims[4] = {block rows, block columns, blocks, values} */
+int vbarms_matrix_dims(vbarms_t h, int32_t which, int32_t level, int64_t *dims);
+/* rb[p+1], cb[q+1]: scalar offsets of row/column blocks; rowptr[p+1], colidx[nb]: block
+ * pattern with ascending columns; vals: blocks in order, each row-major; piv (D, DL only,
+ * may be NULL): GEPP row interchanges, one per scalar row, local to the block. */
+int vbarms_matrix_get(vbarms_t h, int32_t which, int32_t level, int32_t *rb, int32_t *cb,
+                      int64_t *rowptr, int32_t *colidx, double *vals, int32_t *piv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VBARMS_H */

@@ -96,10 +96,10 @@ class BlockMatrix:
     def __init__(self, rb, cb, rowptr, colidx, vals, piv=None):
         self.rb, self.cb, self.rowptr, self.colidx, self.vals, self.piv = rb, cb, rowptr, colidx, vals, piv
         self.p, self.q = len(rb) - 1, len(cb) - 1
-        sizes = [(rb[i + 1] - rb[i]) * (cb[colidx[k] + 1] - cb[colidx[k]])
-                 for i in range(self.p) for k in range(rowptr[i], rowptr[i + 1])]
+        rows = np.repeat(np.arange(self.p), np.diff(rowptr))
+        sizes = (np.diff(rb)[rows].astype(np.int64) * np.diff(cb)[np.asarray(colidx, dtype=np.int64)])
         self.voff = np.zeros(len(colidx) + 1, dtype=np.int64)
-        if sizes:
+        if sizes.size:
             np.cumsum(sizes, out=self.voff[1:])
 
     @property

@@ -1,0 +1,480 @@
+// C ABI of the VBARMS library (declared in include/vbarms.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "factor.h"
+
+using namespace vb;
+
+struct vbarms_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string last_error;
+    int n = 0;
+    int64_t nnz = 0;
+    DBuf<int> perm;             // new position -> original row
+    std::vector<int> bptr;      // host block offsets
+    Panel<double> A;            // compressed matrix P_B A P_B^T
+    bool have_A = false;
+    int precision = VBARMS_F64;
+    std::unique_ptr<Factors<double>> f64;
+    std::unique_ptr<Factors<float>> f32;
+    bool have_factors = false;
+    DevErr err;
+    int err_level = -1, err_block = -1;
+    vbarms_fstats stats{};
+    DBuf<double> wx, wy;        // permuted in/out vectors
+    KrylovWork kw;
+};
+
+namespace {
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit Timer(hipStream_t s_) : s(s_) {
+        VB_HIP(hipEventCreate(&a));
+        VB_HIP(hipEventCreate(&b));
+        VB_HIP(hipEventRecord(a, s));
+    }
+    double stop() {
+        VB_HIP(hipEventRecord(b, s));
+        VB_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        VB_HIP(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+    ~Timer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+template <class F>
+int guarded(vbarms_t h, F &&body) {
+    if (!h) return VBARMS_ERR_ARG;
+    try {
+        h->last_error.clear();
+        VB_HIP(hipSetDevice(h->device));
+        return body();
+    } catch (const VbError &e) {
+        h->last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        h->last_error = "host allocation failed";
+        return VBARMS_ERR_OOM;
+    } catch (...) {
+        h->last_error = "unexpected internal error";
+        return VBARMS_ERR_HIP;
+    }
+}
+
+// converts a device error record into an exception
+void check_dev_err(vbarms_t h, const char *stage) {
+    std::vector<int> rec;
+    to_host(rec, h->err.rec.p, 4, h->stream);
+    if (rec[0] == 0) return;
+    h->err_level = rec[1];
+    h->err_block = rec[2];
+    std::string msg = std::string(stage) + ": ";
+    switch (rec[0]) {
+    case VBARMS_ERR_SINGULAR:
+        msg += "singular pivot block " + std::to_string(rec[2]) + " at level " + std::to_string(rec[1]);
+        break;
+    case VBARMS_ERR_NAN: msg += "NaN or Inf in the matrix (row " + std::to_string(rec[1]) + ")"; break;
+    case VBARMS_ERR_OOM: msg += "capacity exceeded (level " + std::to_string(rec[1]) + ", row " + std::to_string(rec[2]) + ")"; break;
+    default: msg += "device wait limit reached (row " + std::to_string(rec[2]) + ")"; break;
+    }
+    fail(rec[0], msg);
+}
+
+void validate_csr(const vbarms_csr *A) {
+    if (!A || A->n < 0 || A->nnz < 0) fail(VBARMS_ERR_ARG, "invalid CSR descriptor");
+    if (A->n > 0 && (!A->rowptr || (A->nnz > 0 && (!A->col || !A->val))))
+        fail(VBARMS_ERR_ARG, "NULL CSR array");
+}
+
+void finish_partition(vbarms_t h, const vbarms_csr *A, vbarms_cstats *st) {
+    hipStream_t s = h->stream;
+    h->err.reset(s);
+    h->A = Panel<double>();
+    panel_from_csr(A->n, A->rowptr, A->col, A->val, h->perm.p, h->bptr, h->A, h->err.rec.p, s);
+    check_dev_err(h, "compress");
+    h->have_A = true;
+    h->have_factors = false;
+    h->f64.reset();
+    h->f32.reset();
+    int maxb = 0;
+    for (size_t i = 0; i + 1 < h->bptr.size(); ++i) maxb = std::max(maxb, h->bptr[i + 1] - h->bptr[i]);
+    if (st) {
+        st->nblocks = (int)h->bptr.size() - 1;
+        st->max_block = maxb;
+        st->nnz_blocks = h->A.nb;
+        st->av_bd = h->A.nv > 0 ? (double)A->nnz / (double)h->A.nv : 1.0;
+        st->av_bs = st->nblocks > 0 ? (double)A->n / st->nblocks : 0.0;
+    }
+    h->wx.alloc(std::max(A->n, 1));
+    h->wy.alloc(std::max(A->n, 1));
+}
+
+template <class T>
+void factor_impl(vbarms_t h, const vbarms_fparams *p, std::unique_ptr<Factors<T>> &fp) {
+    hipStream_t s = h->stream;
+    fp.reset(new Factors<T>());
+    Factors<T> &f = *fp;
+    const int levels = p->levels;
+    f.lev.reserve(levels + 1);
+    Panel<T> cur;
+    panel_convert<double, T>(h->A, cur, s);
+    h->err.reset(s);
+    for (int l = 0; l < levels; ++l) {
+        if (cur.p == 0) break;
+        Timer tm(s);
+        f.lev.emplace_back();
+        Panel<T> next;
+        factor_level<T>(f.lev[l], std::move(cur), l, p->droptol[l], p->drop_schur, next, h->err.rec.p, s);
+        f.nlev = l + 1;
+        check_dev_err(h, "factor");
+        f.level_ms[l] = tm.stop();
+        cur = std::move(next);
+        if (f.lev[l].nis == 0) break;
+    }
+    f.last.A = std::move(cur);
+    Timer tm(s);
+    factor_last<T>(f.last, p->droptol[levels], f.nlev, h->err.rec.p, s);
+    check_dev_err(h, "last-level ILUT");
+    f.ilut_ms = tm.stop();
+    h->stats.levels = f.nlev;
+    h->stats.last_p = f.last.A.p;
+    for (int l = 0; l < VBARMS_MAX_LEVELS; ++l) h->stats.factor_level_ms[l] = l < f.nlev ? f.level_ms[l] : 0.0;
+    h->stats.ilut_ms = f.ilut_ms;
+    int64_t vals = 0;
+    for (int l = 0; l < f.nlev; ++l) {
+        const Level<T> &L = f.lev[l];
+        std::vector<int64_t> d;
+        to_host(d, L.dlu_off.p + L.nis, 1, s);
+        vals += d[0] + L.G.nv + L.W.nv;
+    }
+    {
+        std::vector<int64_t> d;
+        to_host(d, f.last.dl_off.p + f.last.A.p, 1, s);
+        vals += d[0] + f.last.L.nv + f.last.U.nv;
+    }
+    h->stats.factor_values = vals;
+}
+
+// M^{-1} in the compressed numbering
+void precond_apply(vbarms_t h, const double *x, double *y) {
+    if (h->precision == VBARMS_F32) solve_levels<float>(*h->f32, 0, x, y, h->err.rec.p, h->stream);
+    else solve_levels<double>(*h->f64, 0, x, y, h->err.rec.p, h->stream);
+}
+
+template <class T>
+int export_level_matrix(vbarms_t h, Factors<T> &f, int which, int level, int64_t *dims, int32_t *rb, int32_t *cb,
+                        int64_t *rowptr, int32_t *colidx, double *vals, int32_t *piv) {
+    hipStream_t s = h->stream;
+    const Panel<T> *P = nullptr;
+    if (which == VBARMS_M_LAST) P = &f.last.A;
+    else if (which == VBARMS_M_L) P = &f.last.L;
+    else if (which == VBARMS_M_U) P = &f.last.U;
+    else if (which == VBARMS_M_DL) {
+        int p = f.last.A.p;
+        std::vector<int64_t> off;
+        to_host(off, f.last.dl_off.p, p + 1, s);
+        if (dims) { dims[0] = p; dims[1] = p; dims[2] = p; dims[3] = off[p]; return VBARMS_OK; }
+        for (int i = 0; i <= p; ++i) { rb[i] = f.last.A.h_rb[i]; cb[i] = f.last.A.h_rb[i]; rowptr[i] = i; }
+        for (int i = 0; i < p; ++i) colidx[i] = i;
+        std::vector<T> v;
+        to_host(v, f.last.dl.p, off[p], s);
+        for (int64_t k = 0; k < off[p]; ++k) vals[k] = (double)v[k];
+        if (piv) {
+            std::vector<int> pv;
+            to_host(pv, f.last.dl_piv.p, f.last.A.h_rb[p], s);
+            std::copy(pv.begin(), pv.end(), piv);
+        }
+        return VBARMS_OK;
+    } else {
+        if (level < 0 || level >= f.nlev) fail(VBARMS_ERR_ARG, "level out of range");
+        Level<T> &L = f.lev[level];
+        if (which == VBARMS_M_A) P = &L.A;
+        else if (which == VBARMS_M_AS) P = &L.As;
+        else if (which == VBARMS_M_G) P = &L.G;
+        else if (which == VBARMS_M_W) P = &L.W;
+        else if (which == VBARMS_M_D) {
+            int nis = L.nis;
+            std::vector<int64_t> off;
+            to_host(off, L.dlu_off.p, nis + 1, s);
+            if (dims) { dims[0] = nis; dims[1] = nis; dims[2] = nis; dims[3] = off[nis]; return VBARMS_OK; }
+            for (int i = 0; i <= nis; ++i) { rb[i] = L.h_is_rb[i]; cb[i] = L.h_is_rb[i]; rowptr[i] = i; }
+            for (int i = 0; i < nis; ++i) colidx[i] = i;
+            std::vector<T> v;
+            to_host(v, L.dlu.p, off[nis], s);
+            for (int64_t k = 0; k < off[nis]; ++k) vals[k] = (double)v[k];
+            if (piv) {
+                std::vector<int> pv;
+                to_host(pv, L.dpiv.p, L.n_is, s);
+                std::copy(pv.begin(), pv.end(), piv);
+            }
+            return VBARMS_OK;
+        } else {
+            fail(VBARMS_ERR_ARG, "unknown matrix selector");
+        }
+    }
+    if (dims) {
+        dims[0] = P->p;
+        dims[1] = P->q;
+        dims[2] = P->nb;
+        dims[3] = P->nv;
+        return VBARMS_OK;
+    }
+    std::copy(P->h_rb.begin(), P->h_rb.end(), rb);
+    std::copy(P->h_cb.begin(), P->h_cb.end(), cb);
+    std::vector<int64_t> rp;
+    std::vector<int> ci;
+    std::vector<double> v;
+    panel_export<T>(*P, rp, ci, v, s);
+    std::copy(rp.begin(), rp.end(), rowptr);
+    std::copy(ci.begin(), ci.end(), colidx);
+    std::copy(v.begin(), v.end(), vals);
+    return VBARMS_OK;
+}
+
+template <class T>
+Level<T> &level_of(Factors<T> &f, int level) {
+    if (level < 0 || level >= f.nlev) fail(VBARMS_ERR_ARG, "level out of range");
+    return f.lev[level];
+}
+
+void need_factors(vbarms_t h) {
+    if (!h->have_factors) fail(VBARMS_ERR_STATE, "no factorization: call vbarms_factor first");
+}
+
+}  // namespace
+
+extern "C" {
+
+int vbarms_create(vbarms_t *out, void *hip_stream) {
+    if (!out) return VBARMS_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return VBARMS_ERR_HIP;
+    vbarms_ctx *h = new (std::nothrow) vbarms_ctx();
+    if (!h) return VBARMS_ERR_OOM;
+    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return VBARMS_ERR_HIP; }
+    h->stream = (hipStream_t)hip_stream;
+    int rc = guarded(h, [&] {
+        h->err.reset(h->stream);
+        return VBARMS_OK;
+    });
+    if (rc != VBARMS_OK) { delete h; return rc; }
+    *out = h;
+    return VBARMS_OK;
+}
+
+int vbarms_destroy(vbarms_t h) {
+    if (!h) return VBARMS_ERR_ARG;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+    return VBARMS_OK;
+}
+
+const char *vbarms_last_error(vbarms_t h) { return h ? h->last_error.c_str() : "invalid handle"; }
+
+int vbarms_compress(vbarms_t h, const vbarms_csr *A, double tau, int32_t *perm, int32_t *bptr, vbarms_cstats *st) {
+    return guarded(h, [&] {
+        validate_csr(A);
+        if (!(tau > 0.0 && tau <= 1.0)) fail(VBARMS_ERR_ARG, "tau must lie in (0, 1]");
+        hipStream_t s = h->stream;
+        Timer tm(s);
+        h->n = A->n;
+        h->nnz = A->nnz;
+        h->perm.alloc(std::max(A->n, 1));
+        h->bptr = compress_gpu(A->n, A->rowptr, A->col, tau, h->perm.p, s);
+        finish_partition(h, A, st);
+        if (perm && A->n) VB_HIP(hipMemcpyAsync(perm, h->perm.p, sizeof(int) * A->n, hipMemcpyDeviceToDevice, s));
+        if (bptr) to_device(bptr, h->bptr.data(), h->bptr.size(), s);
+        VB_HIP(hipStreamSynchronize(s));
+        h->stats.compress_ms = tm.stop();
+        h->stats.nnz = A->nnz;
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_set_partition(vbarms_t h, const vbarms_csr *A, const int32_t *perm, const int32_t *bptr, int32_t p,
+                         vbarms_cstats *st) {
+    return guarded(h, [&] {
+        validate_csr(A);
+        if (p < 0 || (A->n > 0 && (!perm || !bptr))) fail(VBARMS_ERR_ARG, "invalid partition");
+        hipStream_t s = h->stream;
+        h->n = A->n;
+        h->nnz = A->nnz;
+        h->perm.alloc(std::max(A->n, 1));
+        if (A->n) VB_HIP(hipMemcpyAsync(h->perm.p, perm, sizeof(int) * A->n, hipMemcpyDeviceToDevice, s));
+        to_host(h->bptr, bptr, p + 1, s);
+        if (h->bptr[0] != 0 || h->bptr[p] != A->n) fail(VBARMS_ERR_ARG, "bptr must run from 0 to n");
+        for (int i = 0; i < p; ++i)
+            if (h->bptr[i + 1] <= h->bptr[i]) fail(VBARMS_ERR_ARG, "empty or decreasing block in bptr");
+        finish_partition(h, A, st);
+        h->stats.nnz = A->nnz;
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_factor(vbarms_t h, const vbarms_fparams *p) {
+    return guarded(h, [&] {
+        if (!p || p->levels < 0 || p->levels > VBARMS_MAX_LEVELS) fail(VBARMS_ERR_ARG, "invalid factor parameters");
+        for (int l = 0; l <= p->levels; ++l)
+            if (!(p->droptol[l] >= 0.0) || !std::isfinite(p->droptol[l])) fail(VBARMS_ERR_ARG, "invalid drop tolerance");
+        if (p->precision != VBARMS_F64 && p->precision != VBARMS_F32) fail(VBARMS_ERR_ARG, "invalid precision");
+        if (!h->have_A) fail(VBARMS_ERR_STATE, "no compressed matrix: call vbarms_compress first");
+        h->have_factors = false;
+        h->err_level = h->err_block = -1;
+        h->f64.reset();
+        h->f32.reset();
+        h->precision = p->precision;
+        Timer tm(h->stream);
+        if (p->precision == VBARMS_F32) factor_impl<float>(h, p, h->f32);
+        else factor_impl<double>(h, p, h->f64);
+        h->stats.factor_ms = tm.stop();
+        h->have_factors = true;
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_error_location(vbarms_t h, int32_t *level, int32_t *block) {
+    if (!h) return VBARMS_ERR_ARG;
+    if (level) *level = h->err_level;
+    if (block) *block = h->err_block;
+    return VBARMS_OK;
+}
+
+int vbarms_apply(vbarms_t h, const double *x, double *y) {
+    return guarded(h, [&] {
+        need_factors(h);
+        if (h->n > 0 && (!x || !y)) fail(VBARMS_ERR_ARG, "NULL vector");
+        hipStream_t s = h->stream;
+        h->err.reset(s);
+        gather_perm(h->n, h->perm.p, x, h->wx.p, s);
+        precond_apply(h, h->wx.p, h->wy.p);
+        scatter_perm(h->n, h->perm.p, h->wy.p, y, s);
+        check_dev_err(h, "apply");
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_spmv(vbarms_t h, const double *x, double *y) {
+    return guarded(h, [&] {
+        if (!h->have_A) fail(VBARMS_ERR_STATE, "no compressed matrix");
+        if (h->n > 0 && (!x || !y)) fail(VBARMS_ERR_ARG, "NULL vector");
+        hipStream_t s = h->stream;
+        gather_perm(h->n, h->perm.p, x, h->wx.p, s);
+        panel_spmv<double>(h->A, h->wx.p, h->wy.p, s);
+        scatter_perm(h->n, h->perm.p, h->wy.p, y, s);
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_solve(vbarms_t h, const double *b, double *x, double tol, int32_t restart, int32_t maxit,
+                 vbarms_sinfo *info) {
+    return guarded(h, [&] {
+        need_factors(h);
+        if (restart < 1 || maxit < 0 || !(tol >= 0.0)) fail(VBARMS_ERR_ARG, "invalid solver parameters");
+        if (h->n > 0 && (!x || !b)) fail(VBARMS_ERR_ARG, "NULL vector");
+        hipStream_t s = h->stream;
+        Timer tm(s);
+        h->err.reset(s);
+        DBuf<double> bc(std::max(h->n, 1)), xc(std::max(h->n, 1));
+        gather_perm(h->n, h->perm.p, b, bc.p, s);
+        gather_perm(h->n, h->perm.p, x, xc.p, s);
+        auto pre = [&](const double *in, double *out) { precond_apply(h, in, out); };
+        int st = fgmres_run(h->A, h->kw, bc.p, xc.p, tol, restart, maxit, pre, info, s);
+        check_dev_err(h, "solve");
+        scatter_perm(h->n, h->perm.p, xc.p, x, s);
+        VB_HIP(hipStreamSynchronize(s));
+        h->stats.solve_ms = tm.stop();
+        return st;
+    });
+}
+
+int vbarms_get_stats(vbarms_t h, vbarms_fstats *st) {
+    if (!h || !st) return VBARMS_ERR_ARG;
+    *st = h->stats;
+    return VBARMS_OK;
+}
+
+int vbarms_num_levels(vbarms_t h, int32_t *levels) {
+    return guarded(h, [&] {
+        need_factors(h);
+        *levels = h->precision == VBARMS_F32 ? h->f32->nlev : h->f64->nlev;
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_level_info(vbarms_t h, int32_t level, int32_t *info) {
+    return guarded(h, [&] {
+        need_factors(h);
+        auto fill = [&](auto &f) {
+            auto &L = level_of(f, level);
+            info[0] = L.p; info[1] = L.n; info[2] = L.nis; info[3] = L.n_is;
+        };
+        if (h->precision == VBARMS_F32) fill(*h->f32); else fill(*h->f64);
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_level_is(vbarms_t h, int32_t level, int32_t *is_list) {
+    return guarded(h, [&] {
+        need_factors(h);
+        auto get = [&](auto &f) {
+            auto &L = level_of(f, level);
+            std::vector<int> v;
+            to_host(v, L.is_list.p, L.nis, h->stream);
+            std::copy(v.begin(), v.end(), is_list);
+        };
+        if (h->precision == VBARMS_F32) get(*h->f32); else get(*h->f64);
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_level_scaling(vbarms_t h, int32_t level, double *s1, double *s2) {
+    return guarded(h, [&] {
+        need_factors(h);
+        auto get = [&](auto &f) {
+            auto &L = level_of(f, level);
+            std::vector<double> v;
+            to_host(v, L.s1.p, L.n, h->stream);
+            std::copy(v.begin(), v.end(), s1);
+            to_host(v, L.s2.p, L.n, h->stream);
+            std::copy(v.begin(), v.end(), s2);
+        };
+        if (h->precision == VBARMS_F32) get(*h->f32); else get(*h->f64);
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_matrix_dims(vbarms_t h, int32_t which, int32_t level, int64_t *dims) {
+    return guarded(h, [&] {
+        need_factors(h);
+        if (!dims) fail(VBARMS_ERR_ARG, "NULL dims");
+        if (h->precision == VBARMS_F32)
+            return export_level_matrix<float>(h, *h->f32, which, level, dims, nullptr, nullptr, nullptr, nullptr,
+                                              nullptr, nullptr);
+        return export_level_matrix<double>(h, *h->f64, which, level, dims, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                           nullptr);
+    });
+}
+
+int vbarms_matrix_get(vbarms_t h, int32_t which, int32_t level, int32_t *rb, int32_t *cb, int64_t *rowptr,
+                      int32_t *colidx, double *vals, int32_t *piv) {
+    return guarded(h, [&] {
+        need_factors(h);
+        if (!rb || !cb || !rowptr || !colidx || !vals) fail(VBARMS_ERR_ARG, "NULL output array");
+        if (h->precision == VBARMS_F32)
+            return export_level_matrix<float>(h, *h->f32, which, level, nullptr, rb, cb, rowptr, colidx, vals, piv);
+        return export_level_matrix<double>(h, *h->f64, which, level, nullptr, rb, cb, rowptr, colidx, vals, piv);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Multilevel factor data shared by the factorization, the solve and the C ABI.
+#pragma once
+
+#include "common.h"
+
+namespace vb {
+
+// One level of the partial block factorization (Sec. 3, Steps 2-4).
+template <class T>
+struct Level {
+    int p = 0, n = 0;             // supernodes / scalar size of A_l
+    int nis = 0, n_is = 0;        // independent-set supernodes / scalar size
+    int nrest = 0, n_rest = 0;    // remaining supernodes / scalar size
+    Panel<T> A;                   // A_l as received (kept for inspection)
+    Panel<T> As;                  // S1 A_l S2
+    DBuf<double> s1, s2;          // [n]
+    DBuf<int> num;                // [p] position in the IS or in the rest
+    DBuf<int> is_flag;            // [p]
+    DBuf<int> is_list, rest_list; // ascending
+    std::vector<int> h_is_rb, h_rest_rb;
+    DBuf<int> is_rb, rest_rb;     // scalar offsets in the IS / rest numbering
+    DBuf<T> dlu;                  // LU of the IS pivot blocks, concatenated
+    DBuf<int64_t> dlu_off;        // [nis+1]
+    DBuf<int> dpiv;               // [n_is] local row interchanges
+    Panel<T> G;                   // L^{-1} P F: IS rows x rest columns
+    Panel<T> W;                   // E U^{-1}:   rest rows x IS columns
+    DBuf<double> y;               // apply workspace [n_is]
+    DBuf<double> t;               // apply workspace [n_is]
+    DBuf<double> g, z;            // apply workspace [n_rest]: next level's right-hand side / solution
+};
+
+// Last level block ILUT factors (Sec. 3, Alg. 3).
+template <class T>
+struct LastLevel {
+    Panel<T> A;                   // matrix handed to the ILUT
+    Panel<T> L, U;                // strictly lower multipliers / strictly upper blocks
+    DBuf<T> dl;                   // LU of the pivot blocks
+    DBuf<int64_t> dl_off;         // [p+1]
+    DBuf<int> dl_piv;             // [n]
+    DBuf<int> done_f, done_b;     // sync-free solve flags (epochs)
+    DBuf<int> tickets;            // [2] ticket counters
+    int epoch = 0;
+    DBuf<double> t;               // solve workspace [n]
+};
+
+template <class T>
+struct Factors {
+    std::vector<Level<T>> lev;
+    LastLevel<T> last;
+    int nlev = 0;
+    double level_ms[VBARMS_MAX_LEVELS] = {0};
+    double ilut_ms = 0;
+};
+
+// device error record: {code, level, block, aux}
+struct DevErr {
+    DBuf<int> rec;
+    void reset(hipStream_t s) {
+        if (!rec.p) rec.alloc(4);
+        VB_HIP(hipMemsetAsync(rec.p, 0, 4 * sizeof(int), s));
+    }
+};
+
+void lfmis(int nv, const int64_t *eptr, const int *elist, const int64_t *eptr2, const int *elist2, int *state,
+           hipStream_t s);
+std::vector<int> compress_gpu(int n, const int64_t *rowptr, const int *col, double tau, int *perm, hipStream_t s);
+void panel_from_csr(int n, const int64_t *rowptr, const int *col, const double *val, const int *perm,
+                    const std::vector<int> &bptr, Panel<double> &out, int *err, hipStream_t s);
+template <class T>
+void panel_spmv_ex(const Panel<T> &a, const double *x, const double *b, double *y, hipStream_t s);
+template <class Tin, class Tout>
+void panel_convert(const Panel<Tin> &src, Panel<Tout> &dst, hipStream_t s);
+
+// Factors level `lvl` of A (consumed), producing the next Schur complement in `next`.
+template <class T>
+void factor_level(Level<T> &L, Panel<T> &&A, int lvl, double droptol, int drop_schur, Panel<T> &next, int *err,
+                  hipStream_t s);
+// Block ILUT of `last.A` with threshold t.
+template <class T>
+void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStream_t s);
+// x = U^{-1} L^{-1} b for the last level (b and x may alias)
+template <class T>
+void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStream_t s);
+// x_l = M_l^{-1} b_l recursively from level `lvl` (vectors in the level's numbering)
+template <class T>
+void solve_levels(Factors<T> &f, int lvl, const double *b, double *x, int *err, hipStream_t s);
+
+}  // namespace vb
+
+#include <functional>
+
+namespace vb {
+
+struct KrylovWork {
+    DBuf<double> V, Z, partial, hdev, nrm;
+    int64_t n = 0;
+    int m = 0;
+    void ensure(int64_t n_, int m_);
+};
+int fgmres_run(const Panel<double> &A, KrylovWork &kw, const double *b, double *x, double tol, int m, int maxit,
+               const std::function<void(const double *, double *)> &precond, vbarms_sinfo *info, hipStream_t s);
+void gather_perm(int n, const int *perm, const double *src, double *dst, hipStream_t s);
+void scatter_perm(int n, const int *perm, const double *src, double *dst, hipStream_t s);
+
+}  // namespace vb

@@ -1,0 +1,57 @@
+// y = A x (or y = b - A x) on the block-row panel layout.
+//
+// Each scalar row is a contiguous run of W_I values whose column list sc is shared by the
+// m_I rows of its block row.  A group of TG lanes strides over one row (coalesced value
+// reads, column indices served from cache for the sibling rows) and reduces with DPP
+// shuffles.  HBM-bound: per call it moves the values, the shared column lists, x and y.
+#include "common.h"
+
+namespace vb {
+
+namespace {
+
+template <class T, int TG>
+__global__ void __launch_bounds__(256) k_spmv(int64_t n, const int *__restrict__ rowblk, const int *__restrict__ rb,
+                                              const int64_t *__restrict__ wp, const int64_t *__restrict__ vp,
+                                              const int *__restrict__ sc, const T *__restrict__ v,
+                                              const double *__restrict__ x, const double *__restrict__ b,
+                                              double *__restrict__ y) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t row = gid / TG;
+    int lane = (int)(gid % TG);
+    double acc = 0.0;
+    if (row < n) {
+        int I = rowblk[row];
+        int rl = (int)(row - rb[I]);
+        int64_t W = wp[I + 1] - wp[I];
+        const T *a = v + vp[I] + rl * W;
+        const int *c = sc + wp[I];
+        for (int64_t j = lane; j < W; j += TG) acc += (double)a[j] * x[c[j]];
+    }
+#pragma unroll
+    for (int off = TG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, TG);
+    if (row < n && lane == 0) y[row] = b ? b[row] - acc : acc;
+}
+
+}  // namespace
+
+template <class T>
+void panel_spmv_ex(const Panel<T> &a, const double *x, const double *b, double *y, hipStream_t s) {
+    int64_t n = a.h_rb.empty() ? 0 : a.h_rb.back();
+    if (n == 0) return;
+    constexpr int TG = 8;
+    k_spmv<T, TG><<<grid_for(n * TG, 256), 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p, x, b, y);
+    VB_LAUNCH_CHECK();
+}
+
+template <class T>
+void panel_spmv(const Panel<T> &a, const double *x, double *y, hipStream_t s) {
+    panel_spmv_ex<T>(a, x, nullptr, y, s);
+}
+
+template void panel_spmv<double>(const Panel<double> &, const double *, double *, hipStream_t);
+template void panel_spmv<float>(const Panel<float> &, const double *, double *, hipStream_t);
+template void panel_spmv_ex<double>(const Panel<double> &, const double *, const double *, double *, hipStream_t);
+template void panel_spmv_ex<float>(const Panel<float> &, const double *, const double *, double *, hipStream_t);
+
+}  // namespace vb

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Integer results (partition, independent sets, block patterns, pivots) must match
+bit for bit; FP64 factors to 1e-10 relative (the kernels keep the oracle's operation
+order and no fused multiply-add, so they usually agree exactly); every solve must reach a
+true relative residual of 1e-8.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1508_02219_amd import synth
+from tests import oracle_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def vb():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_02219_amd import vbarms
+    vbarms.lib()
+    return vbarms
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run_both(vb, orc, s, tau, levels, droptol, drop_schur=1, precision=0):
+    _say(f"[case] {s.name} n={s.n} nnz={s.nnz} tau={tau} levels={levels} t={droptol}")
+    perm_o, bptr_o = orc.compress(s.n, s.rowptr, s.col, tau)
+    o = orc.Oracle(s.n, s.rowptr, s.col, s.val, perm_o, bptr_o, levels, droptol, drop_schur)
+    sv = vb.Solver()
+    rp, ci, va = vb.csr_to_device(s)
+    perm, bptr, st = sv.compress(rp, ci, va, tau)
+    np.testing.assert_array_equal(perm.cpu().numpy(), perm_o)
+    np.testing.assert_array_equal(bptr.cpu().numpy(), bptr_o)
+    err = None
+    try:
+        sv.factor(levels, droptol, drop_schur, precision)
+    except vb.VbarmsError as e:
+        err = e
+    return o, sv, (rp, ci, va), st, err
+
+
+def _same_matrix(g, o, rtol=RTOL, what=""):
+    np.testing.assert_array_equal(g.rb, o.rb, err_msg=f"{what} row blocks")
+    np.testing.assert_array_equal(g.cb, o.cb, err_msg=f"{what} column blocks")
+    np.testing.assert_array_equal(g.rowptr, o.rowptr, err_msg=f"{what} block pattern")
+    np.testing.assert_array_equal(g.colidx, o.colidx, err_msg=f"{what} block columns")
+    assert g.vals.shape == o.vals.shape, what
+    if o.vals.size:
+        scale = max(np.abs(o.vals).max(), 1e-300)
+        assert np.abs(g.vals - o.vals).max() <= rtol * scale, f"{what}: max diff {np.abs(g.vals - o.vals).max()}"
+    if o.piv is not None:
+        np.testing.assert_array_equal(g.piv, o.piv, err_msg=f"{what} pivots")
+
+
+def _check_all_factors(vb, orc, o, sv, rtol=RTOL):
+    assert sv.num_levels() == o.nlevels
+    for lvl in range(o.nlevels):
+        assert sv.level_info(lvl) == o.level_info(lvl)
+        np.testing.assert_array_equal(sv.level_is(lvl), o.level_is(lvl))
+        s1, s2 = sv.level_scaling(lvl)
+        o1, o2 = o.level_scaling(lvl)
+        np.testing.assert_allclose(s1, o1, rtol=rtol)
+        np.testing.assert_allclose(s2, o2, rtol=rtol)
+        for w, name in ((vb.M_A, "A"), (vb.M_AS, "AS"), (vb.M_D, "D"), (vb.M_G, "G"), (vb.M_W, "W")):
+            _same_matrix(sv.matrix(w, lvl), o.matrix(w, lvl), rtol, f"level {lvl} {name}")
+    for w, name in ((vb.M_LAST, "last"), (vb.M_L, "L"), (vb.M_U, "U"), (vb.M_DL, "DL")):
+        _same_matrix(sv.matrix(w), o.matrix(w), rtol, name)
+
+
+SYSTEMS = {
+    "grid14_perturbed": lambda: (synth.grid_system(6, 5, 4, ell=5, stencil="14rand", perturb=0.10, seed=101), 0.8),
+    "grid7_cfg1_recipe": lambda: (synth.config_system(1, 0.6), 1.0),
+    "upwind_variable_blocks": lambda: (synth.upwind_system(7, 6, 5, seed=103), 1.0),
+    "pivoting_shift": lambda: (H.node_rows_reversed(synth.grid_system(5, 4, 4, ell=4, stencil="14rand", seed=104),
+                                                    "shift"), 1.0),
+    "random_twins": lambda: (synth.random_pattern_matrix(300, 0.02, twins=80, seed=105, diag=10.0), 1.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SYSTEMS))
+@pytest.mark.parametrize("levels,t", [(0, 1e-3), (1, 1e-3), (3, 1e-4), (2, 0.0)])
+def test_factors_match_oracle(vb, orc, name, levels, t):
+    s, tau = SYSTEMS[name]()
+    o, sv, A, st, err = _run_both(vb, orc, s, tau, levels, t)
+    assert err is None and o.status == 0, err
+    _check_all_factors(vb, orc, o, sv)
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.9133, 0.8, 0.6180339, 0.45])
+@pytest.mark.parametrize("seed", [201, 202])
+def test_compression_matches_oracle(vb, orc, tau, seed):
+    s = synth.grid_system(7, 6, 5, ell=5, stencil="14rand", perturb=0.15, seed=seed)
+    _say(f"[case] compress {s.name} tau={tau}")
+    perm_o, bptr_o = orc.compress(s.n, s.rowptr, s.col, tau)
+    sv = vb.Solver()
+    rp, ci, va = vb.csr_to_device(s)
+    perm, bptr, st = sv.compress(rp, ci, va, tau)
+    np.testing.assert_array_equal(perm.cpu().numpy(), perm_o)
+    np.testing.assert_array_equal(bptr.cpu().numpy(), bptr_o)
+    assert st.nblocks == len(bptr_o) - 1
+    assert st.max_block == int(np.diff(bptr_o).max())
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.7071, 0.5])
+def test_compression_random_patterns(vb, orc, tau):
+    for seed in range(4):
+        s = synth.random_pattern_matrix(400, 0.015, twins=150, seed=300 + seed, diag=5.0)
+        _say(f"[case] compress {s.name} tau={tau}")
+        perm_o, bptr_o = orc.compress(s.n, s.rowptr, s.col, tau)
+        sv = vb.Solver()
+        perm, bptr, st = sv.compress(*vb.csr_to_device(s), tau)
+        np.testing.assert_array_equal(perm.cpu().numpy(), perm_o)
+        np.testing.assert_array_equal(bptr.cpu().numpy(), bptr_o)
+
+
+def test_drop_schur_off_matches_oracle(vb, orc):
+    s = synth.grid_system(5, 5, 4, ell=3, stencil="14rand", perturb=0.1, seed=22)
+    o, sv, A, st, err = _run_both(vb, orc, s, 0.8, 2, [0.05, 0.05, 0.0], drop_schur=0)
+    assert err is None
+    _check_all_factors(vb, orc, o, sv)
+
+
+@pytest.mark.parametrize("name", sorted(SYSTEMS))
+def test_apply_and_spmv_match(vb, orc, name):
+    import torch
+    s, tau = SYSTEMS[name]()
+    o, sv, A, st, err = _run_both(vb, orc, s, tau, 2, 1e-3)
+    assert err is None
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(s.n)
+    xd = torch.as_tensor(x, device="cuda")
+    y = sv.apply(xd).cpu().numpy()
+    yo = o.apply(x)
+    assert np.abs(y - yo).max() <= RTOL * np.abs(yo).max()
+    ax = sv.spmv(xd).cpu().numpy()
+    import scipy.sparse as sp
+    a = sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n))
+    assert np.abs(ax - a @ x).max() <= 1e-13 * np.abs(a @ x).max()
+
+
+def test_exact_factorization_gives_exact_inverse(vb, orc):
+    import torch
+    s = synth.grid_system(4, 4, 3, ell=3, stencil="14rand", perturb=0.1, seed=41)
+    o, sv, A, st, err = _run_both(vb, orc, s, 0.8, 3, 0.0)
+    x = np.random.default_rng(1).standard_normal(s.n)
+    y = sv.apply(torch.as_tensor(x, device="cuda")).cpu().numpy()
+    ye = np.linalg.solve(s.dense(), x)
+    assert np.abs(y - ye).max() <= 1e-10 * np.abs(ye).max()
+
+
+@pytest.mark.parametrize("name", sorted(SYSTEMS))
+def test_solve_reaches_tolerance(vb, orc, name):
+    import torch
+    s, tau = SYSTEMS[name]()
+    o, sv, A, st, err = _run_both(vb, orc, s, tau, 2, 1e-3)
+    b = torch.as_tensor(s.b, device="cuda")
+    x, info = sv.solve(b, tol=1e-8, restart=30, maxit=1000)
+    assert info.status == 0
+    import scipy.sparse as sp
+    a = sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n))
+    xh = x.cpu().numpy()
+    rel = np.linalg.norm(s.b - a @ xh) / np.linalg.norm(s.b)
+    assert rel <= 1e-8
+    assert abs(rel - info.true_relres) <= 1e-10
+    xo, st_o, its_o, rel_o, _ = orc.fgmres(s.n, s.rowptr, s.col, s.val, s.b, o, 1e-8, 30, 1000)
+    assert st_o == 0 and abs(info.iters - its_o) <= 2
+
+
+def test_solve_not_converged_and_restarts(vb, orc):
+    import torch
+    s = synth.grid_system(6, 6, 6, ell=5, stencil="14rand", perturb=0.1, seed=52)
+    o, sv, A, st, err = _run_both(vb, orc, s, 0.8, 2, 5e-2)
+    b = torch.as_tensor(s.b, device="cuda")
+    x, info = sv.solve(b, tol=1e-8, restart=5, maxit=1000)
+    assert info.status == 0 and info.iters > 5 and info.restarts >= 1
+    x, info = sv.solve(b, tol=1e-8, restart=5, maxit=2)
+    assert info.status == vb.NOT_CONVERGED and info.iters == 2
+
+
+def test_float32_factors_reach_fp64_tolerance(vb, orc):
+    import torch
+    s = synth.grid_system(8, 8, 8, ell=5, stencil="14rand", perturb=0.10, seed=2)
+    _say(f"[case] fp32 {s.name}")
+    sv = vb.Solver()
+    sv.compress(*vb.csr_to_device(s), 0.8)
+    sv.factor(3, 1e-4, 1, vb.F32)
+    x, info = sv.solve(torch.as_tensor(s.b, device="cuda"), tol=1e-8, restart=50)
+    assert info.status == 0 and info.true_relres <= 1e-8
+
+
+# ----------------------------------------------------------------------------------------
+# edge cases and error handling
+# ----------------------------------------------------------------------------------------
+def test_block_diagonal_matrix_empties_schur(vb, orc):
+    # no coupling between nodes: every supernode is independent, the Schur complement is empty
+    s = synth.grid_system(1, 1, 1, ell=5, stencil="7pt", seed=3)
+    s2 = synth.random_pattern_matrix(40, 0.0, seed=4)  # diagonal only
+    for sys_ in (s, s2):
+        o, sv, A, st, err = _run_both(vb, orc, sys_, 1.0, 2, 1e-3)
+        assert err is None
+        _check_all_factors(vb, orc, o, sv)
+
+
+def test_singular_pivot_reported_like_oracle(vb, orc):
+    s = synth.grid_system(3, 3, 2, ell=3, stencil="7pt", seed=61)
+    val = s.val.copy()
+    for r in range(3):
+        for k in range(s.rowptr[r], s.rowptr[r + 1]):
+            if s.col[k] < 3:
+                val[k] = 0.0
+    s.val = val
+    o, sv, A, st, err = _run_both(vb, orc, s, 1.0, 1, 1e-3)
+    assert o.status == orc.ERR_SINGULAR
+    assert err is not None and err.code == vb.ERR_SINGULAR
+    assert sv.error_location() == (o.err_level, o.err_block)
+
+
+def test_argument_and_state_errors(vb):
+    import torch
+    s = synth.grid_system(3, 3, 3, ell=2, stencil="7pt", seed=5)
+    sv = vb.Solver()
+    rp, ci, va = vb.csr_to_device(s)
+    for tau in (0.0, 1.5, float("nan")):
+        with pytest.raises(vb.VbarmsError) as e:
+            sv.compress(rp, ci, va, tau)
+        assert e.value.code == vb.ERR_ARG
+    with pytest.raises(vb.VbarmsError) as e:
+        sv.factor(1, 1e-3)
+    assert e.value.code == vb.ERR_STATE
+    sv.compress(rp, ci, va, 1.0)
+    with pytest.raises(vb.VbarmsError) as e:
+        sv.apply(torch.zeros(s.n, dtype=torch.float64, device="cuda"))
+    assert e.value.code == vb.ERR_STATE
+    with pytest.raises(vb.VbarmsError) as e:
+        sv.factor(1, -1.0)
+    assert e.value.code == vb.ERR_ARG
+    bad = va.clone()
+    bad[3] = float("nan")
+    with pytest.raises(vb.VbarmsError) as e:
+        sv.compress(rp, ci, bad, 1.0)
+    assert e.value.code == vb.ERR_NAN
+    sv.compress(rp, ci, va, 1.0)
+    sv.factor(1, 1e-3)
+    b = torch.as_tensor(s.b, device="cuda")
+    b[0] = float("inf")
+    with pytest.raises(vb.VbarmsError) as e:
+        sv.solve(b)
+    assert e.value.code == vb.ERR_NAN
+
+
+def test_zero_rhs_and_repeated_calls(vb):
+    import torch
+    s = synth.grid_system(4, 4, 4, ell=3, stencil="14rand", perturb=0.1, seed=6)
+    sv = vb.Solver()
+    sv.compress(*vb.csr_to_device(s), 0.8)
+    sv.factor(2, 1e-3)
+    x, info = sv.solve(torch.zeros(s.n, dtype=torch.float64, device="cuda"))
+    assert info.status == 0 and float(x.abs().max()) == 0.0
+    b = torch.as_tensor(s.b, device="cuda")
+    x1, i1 = sv.solve(b)
+    x2, i2 = sv.solve(b)
+    assert torch.equal(x1, x2) and i1.iters == i2.iters  # deterministic
+    y1 = sv.apply(b)
+    y2 = sv.apply(b)
+    assert torch.equal(y1, y2)

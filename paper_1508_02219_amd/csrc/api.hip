@@ -54,6 +54,7 @@ struct Timer {
 template <class F>
 int guarded(vbarms_t h, F &&body) {
     if (!h) return VBARMS_ERR_ARG;
+    StreamScope scope(h->stream);  // device buffers are allocated and freed on the handle's stream
     try {
         h->last_error.clear();
         VB_HIP(hipSetDevice(h->device));
@@ -84,7 +85,7 @@ void check_dev_err(vbarms_t h, const char *stage) {
         break;
     case VBARMS_ERR_NAN: msg += "NaN or Inf in the matrix (row " + std::to_string(rec[1]) + ")"; break;
     case VBARMS_ERR_OOM: msg += "capacity exceeded (level " + std::to_string(rec[1]) + ", row " + std::to_string(rec[2]) + ")"; break;
-    default: msg += "device wait limit reached (row " + std::to_string(rec[2]) + ")"; break;
+    default: msg += "inconsistent factor data (level " + std::to_string(rec[1]) + ", row " + std::to_string(rec[2]) + ")"; break;
     }
     fail(rec[0], msg);
 }
@@ -263,6 +264,14 @@ int vbarms_create(vbarms_t *out, void *hip_stream) {
     if (!h) return VBARMS_ERR_OOM;
     if (hipGetDevice(&h->device) != hipSuccess) { delete h; return VBARMS_ERR_HIP; }
     h->stream = (hipStream_t)hip_stream;
+    {
+        // keep freed stream-ordered memory in the device pool instead of returning it at every sync
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, h->device) == hipSuccess && pool) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+    }
     int rc = guarded(h, [&] {
         h->err.reset(h->stream);
         return VBARMS_OK;
@@ -275,8 +284,12 @@ int vbarms_create(vbarms_t *out, void *hip_stream) {
 int vbarms_destroy(vbarms_t h) {
     if (!h) return VBARMS_ERR_ARG;
     (void)hipSetDevice(h->device);
-    (void)hipStreamSynchronize(h->stream);
-    delete h;
+    hipStream_t s = h->stream;
+    {
+        StreamScope scope(s);  // buffers are released in stream order
+        delete h;
+    }
+    (void)hipStreamSynchronize(s);
     return VBARMS_OK;
 }
 

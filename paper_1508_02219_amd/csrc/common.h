@@ -35,7 +35,21 @@ struct VbError {
 
 // ---------------------------------------------------------------------------------
 // Device buffers
+//
+// Every buffer is allocated and freed in stream order on the stream of the API call in
+// progress (cur_stream()), so a buffer that goes out of scope is released only after
+// every kernel enqueued before the release has finished with it.
 // ---------------------------------------------------------------------------------
+inline hipStream_t &cur_stream() {
+    static thread_local hipStream_t s = nullptr;
+    return s;
+}
+struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t s) : prev(cur_stream()) { cur_stream() = s; }
+    ~StreamScope() { cur_stream() = prev; }
+};
+
 template <class T>
 struct DBuf {
     T *p = nullptr;
@@ -54,7 +68,7 @@ struct DBuf {
         release();
         n = count;
         if (count) {
-            hipError_t e = hipMalloc(&p, count * sizeof(T));
+            hipError_t e = hipMallocAsync((void **)&p, count * sizeof(T), cur_stream());
             if (e != hipSuccess) {
                 p = nullptr;
                 n = 0;
@@ -67,7 +81,7 @@ struct DBuf {
         if (count > n) alloc(count);
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) (void)hipFreeAsync(p, cur_stream());
         p = nullptr;
         n = 0;
     }

@@ -37,9 +37,10 @@ struct LastLevel {
     DBuf<T> dl;                   // LU of the pivot blocks
     DBuf<int64_t> dl_off;         // [p+1]
     DBuf<int> dl_piv;             // [n]
-    DBuf<int> done_f, done_b;     // sync-free solve flags (epochs)
-    DBuf<int> tickets;            // [2] ticket counters
-    int epoch = 0;
+    std::vector<int> lorder, lptr;  // forward sweep: block rows sorted by level, level offsets
+    std::vector<int> uorder, uptr;  // backward sweep
+    DBuf<int> d_lorder, d_uorder;   // device copies of the two orders
+    int waves = 0;                  // kernel launches the factorization took
     DBuf<double> t;               // solve workspace [n]
 };
 

@@ -1,20 +1,17 @@
-// Last-level block ILUT (Sec. 3, Alg. 3, IKJ order) and its triangular solves.
+// Last-level block ILUT (Sec. 3, Alg. 3, IKJ order) and its block triangular solves.
 //
-// Factorization: a persistent kernel whose workgroups take block rows in ascending order
-// from a ticket counter.  Row i is eliminated against the finished rows k < i present in
-// its working row, smallest k first (fill included), exactly like the sequential IKJ
-// loop; before using row k it waits for row k's completion flag.  Because rows are
-// ticketed in ascending order, every row waited on is already owned by a running
-// workgroup, so the waits always end.  The working row lives in an LDS hash map
-// (block column -> list slot) with its dense blocks in a per-workgroup global scratch.
-// Finished rows are appended to L/U pools and compacted into panels afterwards.
+// Factorization in dependency waves.  Every block row keeps its working row (block list,
+// per-block state and dense blocks) in HBM.  One launch processes all unfinished rows: a
+// row eliminates, in ascending column order exactly like the sequential IKJ loop, every
+// block left of its diagonal whose row was finished in an EARLIER launch; when the next
+// block to eliminate belongs to a row that is not finished yet, the row stops and
+// resumes in the next launch.  Data of other rows is only read across a kernel boundary,
+// so no wait, flag protocol or fence is needed inside a kernel.  The smallest unfinished
+// row can never stop, so every launch finishes at least one row.  Finished rows append
+// their L and U blocks to pools, compacted into panels at the end.
 //
-// Solves: sync-free block substitution, one wavefront per block row taken in dependency
-// order from a ticket counter (ascending for L, descending for U), each waiting on the
-// completion flags of the rows it reads.
-//
-// Every wait has an abort flag and a wall-clock limit, so a fault in the dependency data
-// ends the kernel with an error instead of a hang.
+// Solves: level scheduling from the final patterns of L and U; one launch per level, one
+// wavefront per block row of the level.
 #include <algorithm>
 #include <climits>
 
@@ -25,12 +22,15 @@ namespace vb {
 namespace {
 
 constexpr int kIlutThreads = 256;
-constexpr int kCapB = 1024;       // blocks in one working row
-constexpr int kHashCap = 2048;    // LDS hash slots (power of two, > 2 kCapB / 2)
+constexpr int kHashCap = 2048;  // LDS hash slots: at most kMaxRowBlocks entries
+constexpr int kMaxRowBlocks = 1024;
 
 struct IlutRowRec {
     int64_t lb, lv, ub, uv;  // block / value offsets in the pools
     int lc, lw, uc, uw;      // block counts and panel widths
+};
+struct RowState {
+    int nb, used, last_k, status;  // status: 0 not started, 1 started, 2 finished
 };
 
 __device__ inline int h_find(const int *keys, const int *vals, int key) {
@@ -51,260 +51,273 @@ __device__ inline void h_insert(int *keys, int *vals, int key, int val) {
     }
 }
 
-__device__ inline bool wait_flag(const int *flag, int epoch, int *abort, int *err, unsigned long long limit, int row) {
-    unsigned long long t0 = wall_clock64();
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-        if (wall_clock64() - t0 > limit) {
-            dev_set_error(err, VBARMS_ERR_HIP, 1000, row);
-            __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    return true;
-}
-
+// One wave of the block ILUT: one workgroup per unfinished row in act[].
 template <class T>
-__global__ void __launch_bounds__(kIlutThreads) k_ilut(
-    int p, const int *rb, const int64_t *rp, const int *ci, const int *co, const int64_t *wp, const int64_t *vp,
-    const T *av, double droptol, int *ticket, int *done, int epoch, int *abort, int *err, unsigned long long limit,
-    T *scratch, int64_t capv, T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec, int *lci, int *lco, T *lv,
-    int *uci, int *uco, T *uv, int64_t *cursors, int64_t capb_pool, int64_t capv_pool, int lvl) {
+__global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
+    int launch, int p, const int *act, const int *rb, const int64_t *rp, const int *ci, const int *co, const int64_t *wp,
+    const int64_t *vp, const T *av, double droptol, int *done, RowState *rs, const int64_t *boff, const int64_t *voff,
+    int *wcols, int *woffs, unsigned char *west, T *wvals, T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec,
+    int *lci, int *lco, T *lv, int *uci, int *uco, T *uv, int64_t *cursors, int64_t capb_pool, int64_t capv_pool,
+    int *err, int lvl) {
     __shared__ int hkeys[kHashCap], hvals[kHashCap];
-    __shared__ int wcol[kCapB];
-    __shared__ int woff[kCapB];
-    __shared__ unsigned char wst[kCapB];  // 0 pending, 1 eliminated, 2 dropped
-    __shared__ int s_row, s_n, s_used, s_min, s_flag, s_abort;
+    __shared__ int s_nb, s_used, s_last, s_status, s_min, s_flag, s_stop;
     __shared__ int s_lc, s_lw, s_uc, s_uw;
     __shared__ int64_t s_lb, s_lv, s_ub, s_uv;
     const int t = threadIdx.x;
-    T *w = scratch + (int64_t)blockIdx.x * capv;
+    const int i = act[blockIdx.x];
+    const int m = rb[i + 1] - rb[i];
+    const int64_t B0 = boff[i], CB = boff[i + 1] - boff[i];
+    const int64_t V0 = voff[i], CV = voff[i + 1] - voff[i];
+    int *cols = wcols + B0;
+    int *offs = woffs + B0;
+    unsigned char *est = west + B0;  // 0 pending, 1 eliminated, 2 dropped (3/4 at output: kept L/U)
+    T *w = wvals + V0;
+    if (t == 0) {
+        RowState r = rs[i];
+        s_nb = r.nb;
+        s_used = r.used;
+        s_last = r.last_k;
+        s_status = r.status;
+        s_stop = 0;
+        if (r.status == 0) {
+            int nA = (int)(rp[i + 1] - rp[i]);
+            int64_t W = wp[i + 1] - wp[i];
+            if (nA > CB || nA > kMaxRowBlocks || (int64_t)m * W > CV) {
+                dev_set_error(err, VBARMS_ERR_OOM, lvl, i);
+                s_stop = 1;
+            }
+            s_nb = nA;
+            s_used = (int)(m * W);
+            s_last = -1;
+        }
+    }
+    __syncthreads();
+    if (s_stop) return;
+    if (s_status == 0) {
+        // first visit: row i of A, one entry per block, blocks stored contiguously
+        const int64_t b0 = rp[i];
+        for (int e = t; e < s_nb; e += kIlutThreads) {
+            cols[e] = ci[b0 + e];
+            offs[e] = m * co[b0 + e];
+            est[e] = 0;
+        }
+        const int64_t W = wp[i + 1] - wp[i];
+        const T *A = av + vp[i];
+        for (int64_t c = t; c < W; c += kIlutThreads) {
+            int64_t b = dev_floor32(co, b0, rp[i + 1], (int)c);
+            int nJ = (b + 1 < rp[i + 1] ? co[b + 1] : (int)W) - co[b];
+            int local = (int)(c - co[b]);
+            int off = m * co[b];
+            for (int r = 0; r < m; ++r) w[off + r * nJ + local] = A[r * W + c];
+        }
+    }
+    for (int h = t; h < kHashCap; h += kIlutThreads) hkeys[h] = -1;
+    __syncthreads();
+    for (int e = t; e < s_nb; e += kIlutThreads) h_insert(hkeys, hvals, cols[e], e);
+    __syncthreads();
 
     for (;;) {
-        if (t == 0) s_row = atomicAdd(ticket, 1);
+        if (t == 0) s_min = INT_MAX;
         __syncthreads();
-        const int i = s_row;
-        if (i >= p) break;
-        const int m = rb[i + 1] - rb[i];
-        for (int h = t; h < kHashCap; h += kIlutThreads) hkeys[h] = -1;
+        for (int e = t; e < s_nb; e += kIlutThreads) {
+            int K = cols[e];
+            if (K < i && K > s_last && est[e] == 0) atomicMin(&s_min, K);
+        }
+        __syncthreads();
+        const int k = s_min;
+        if (k == INT_MAX) break;
         if (t == 0) {
-            int nA = (int)(rp[i + 1] - rp[i]);
-            s_abort = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (nA > kCapB || (int64_t)m * (wp[i + 1] - wp[i]) > capv) {
-                dev_set_error(err, VBARMS_ERR_OOM, lvl, i);
-                __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_abort = 1;
-            }
-            s_n = nA;
-            s_used = (int)(m * (wp[i + 1] - wp[i]));
-        }
-        __syncthreads();
-        if (!s_abort) {
-            // load row i: list slot e = block e of the row, blocks stored contiguously
-            const int64_t b0 = rp[i];
-            for (int e = t; e < s_n; e += kIlutThreads) {
-                wcol[e] = ci[b0 + e];
-                woff[e] = m * co[b0 + e];
-                wst[e] = 0;
-                h_insert(hkeys, hvals, ci[b0 + e], e);
-            }
-            const int64_t W = wp[i + 1] - wp[i];
-            const T *A = av + vp[i];
-            for (int64_t c = t; c < W; c += kIlutThreads) {
-                int64_t b = dev_floor32(co, b0, rp[i + 1], (int)c);
-                int nJ = (b + 1 < rp[i + 1] ? co[b + 1] : (int)W) - co[b];
-                int local = (int)(c - co[b]);
-                int off = m * co[b];
-                for (int r = 0; r < m; ++r) w[off + r * nJ + local] = A[r * W + c];
-            }
-        }
-        __syncthreads();
-        int last_k = -1;
-        while (!s_abort) {
-            if (t == 0) s_min = INT_MAX;
-            __syncthreads();
-            for (int e = t; e < s_n; e += kIlutThreads) {
-                int K = wcol[e];
-                if (K < i && K > last_k && wst[e] == 0) atomicMin(&s_min, K);
-            }
-            __syncthreads();
-            const int k = s_min;
-            if (k == INT_MAX) break;
-            last_k = k;
-            const int ek = h_find(hkeys, hvals, k);
-            if (t == 0) {
-                if (!wait_flag(&done[k], epoch, abort, err, limit, i)) s_abort = 1;
-            }
-            __syncthreads();
-            if (s_abort) break;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const int mk = rb[k + 1] - rb[k];
-            const IlutRowRec rk = rec[k];
-            // row k's record must describe pool ranges; anything else is reported, not used
-            if (t == 0) {
-                bool ok = ek >= 0 && ek < s_n && rk.uc >= 0 && rk.ub >= 0 && rk.ub + rk.uc <= capb_pool &&
-                          rk.uw >= 0 && rk.uv >= 0 && rk.uv + (int64_t)mk * rk.uw <= capv_pool &&
-                          (rk.uc == 0) == (rk.uw == 0);
-                for (int q = 0; q < mk; ++q) {
-                    int pq = dl_piv[rb[k] + q];
-                    ok = ok && pq >= q && pq < mk;
-                }
-                if (!ok) {
-                    dev_set_error(err, VBARMS_ERR_HIP, 3001, i);
-                    __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s_abort = 1;
-                }
-            }
-            __syncthreads();
-            if (s_abort) break;
-            T *M = w + woff[ek];
-            const T *dk = dl + dl_off[k];
-            if (t < m) {
-                dev_row_solve_u<T>(mk, dk, M + t * mk, 1);
-                dev_row_solve_lp<T>(mk, dk, dl_piv + rb[k], M + t * mk, 1);
-            }
-            __syncthreads();
-            if (t == 0) s_flag = dev_drop<T>(m, mk, M, mk, droptol);
-            __syncthreads();
+            // row k is usable only if it was finished by an earlier launch
+            const int dk = done[k];
+            s_flag = (dk > 0 && dk < launch) ? 1 : 0;
             if (s_flag) {
-                if (t == 0) wst[ek] = 2;
-                __syncthreads();
+                // the finished row must describe ranges inside the pools
+                const IlutRowRec r = rec[k];
+                const int mk0 = rb[k + 1] - rb[k];
+                int e0 = h_find(hkeys, hvals, k);
+                bool ok = e0 >= 0 && e0 < s_nb && r.uc >= 0 && r.ub >= 0 && r.ub + r.uc <= capb_pool && r.uw >= 0 &&
+                          r.uv >= 0 && r.uv + (int64_t)mk0 * r.uw <= capv_pool;
+                if (!ok) {
+                    dev_set_error(err, VBARMS_ERR_HIP, lvl, i);
+                    s_flag = 2;
+                }
+            }
+        }
+        __syncthreads();
+        if (s_flag != 1) {
+            // not finished yet: keep the state and resume in the next launch
+            if (t == 0 && s_flag == 0) rs[i] = RowState{s_nb, s_used, s_last, 1};
+            return;
+        }
+        const int ek = h_find(hkeys, hvals, k);
+        const int mk = rb[k + 1] - rb[k];
+        const IlutRowRec rk = rec[k];
+        T *M = w + offs[ek];
+        const T *dk_lu = dl + dl_off[k];
+        if (t < m) {
+            dev_row_solve_u<T>(mk, dk_lu, M + t * mk, 1);
+            dev_row_solve_lp<T>(mk, dk_lu, dl_piv + rb[k], M + t * mk, 1);
+        }
+        __syncthreads();
+        if (t == 0) s_flag = dev_drop<T>(m, mk, M, mk, droptol);
+        __syncthreads();
+        if (s_flag) {
+            if (t == 0) {
+                est[ek] = 2;
+                s_last = k;
+            }
+            __syncthreads();
+            continue;
+        }
+        if (t == 0) est[ek] = 1;
+        // fill: blocks of U row k not yet in the working row
+        for (int b = t; b < rk.uc; b += kIlutThreads) {
+            int J = uci[rk.ub + b];
+            if (J <= k || J >= p) {
+                dev_set_error(err, VBARMS_ERR_HIP, lvl, i);
+                s_stop = 1;
                 continue;
             }
-            if (t == 0) wst[ek] = 1;
-            // fill: blocks of U row k not yet in the working row
-            for (int b = t; b < rk.uc; b += kIlutThreads) {
-                int J = uci[rk.ub + b];
-                if (J <= k || J >= p) {
-                    dev_set_error(err, VBARMS_ERR_HIP, 3002, i);
-                    __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s_abort = 1;
-                    continue;
-                }
-                if (h_find(hkeys, hvals, J) >= 0) continue;
-                int nJ = rb[J + 1] - rb[J];
-                int e = atomicAdd(&s_n, 1);
-                int off = atomicAdd(&s_used, m * nJ);
-                if (e >= kCapB || (int64_t)off + m * nJ > capv) {
-                    dev_set_error(err, VBARMS_ERR_OOM, lvl, i);
-                    __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s_abort = 1;
-                    continue;
-                }
-                wcol[e] = J;
-                woff[e] = off;
-                wst[e] = 0;
-                for (int q = 0; q < m * nJ; ++q) w[off + q] = T(0);
-                h_insert(hkeys, hvals, J, e);
+            if (h_find(hkeys, hvals, J) >= 0) continue;
+            int nJ = rb[J + 1] - rb[J];
+            int e = atomicAdd(&s_nb, 1);
+            int off = atomicAdd(&s_used, m * nJ);
+            if (e >= CB || e >= kMaxRowBlocks || (int64_t)off + m * nJ > CV) {
+                dev_set_error(err, VBARMS_ERR_OOM, lvl, i);
+                s_stop = 1;
+                continue;
             }
-            __syncthreads();
-            if (s_abort) break;
-            // w_J -= M U_kJ for every block J of U row k
-            const T *U = uv + rk.uv;
-            const int UW = rk.uw;
-            for (int c = t; c < UW; c += kIlutThreads) {
-                int64_t b = dev_floor32(uco, rk.ub, rk.ub + rk.uc, c);
-                int J = uci[b];
-                int nJ = rb[J + 1] - rb[J];
-                int local = c - uco[b];
-                int e = h_find(hkeys, hvals, J);
-                if (e < 0 || local < 0 || local >= nJ) {
-                    dev_set_error(err, VBARMS_ERR_HIP, 3003, i);
-                    continue;
-                }
-                T *wj = w + woff[e] + local;
-                for (int r = 0; r < m; ++r) {
-                    T acc = wj[r * nJ];
-                    for (int q = 0; q < mk; ++q) acc = acc - M[r * mk + q] * U[q * UW + c];
-                    wj[r * nJ] = acc;
-                }
-            }
-            __syncthreads();
+            cols[e] = J;
+            offs[e] = off;
+            est[e] = 0;
+            for (int q = 0; q < m * nJ; ++q) w[off + q] = T(0);
+            h_insert(hkeys, hvals, J, e);
         }
         __syncthreads();
-        // finalize row i
-        if (!s_abort) {
-            if (t == 0) {
-                s_lc = s_lw = s_uc = s_uw = 0;
-                int ei = h_find(hkeys, hvals, i);
-                T *d = dl + dl_off[i];
-                if (ei < 0) {
-                    dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, i);
-                    for (int q = 0; q < m * m; ++q) d[q] = T(0);
-                } else {
-                    for (int q = 0; q < m * m; ++q) d[q] = w[woff[ei] + q];
-                    if (!dev_gepp<T>(m, d, dl_piv + rb[i])) dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, i);
-                }
+        if (s_stop) return;
+        // w_J -= M U_kJ for every block J of U row k
+        const T *U = uv + rk.uv;
+        const int UW = rk.uw;
+        for (int c = t; c < UW; c += kIlutThreads) {
+            int64_t b = dev_floor32(uco, rk.ub, rk.ub + rk.uc, c);
+            int J = uci[b];
+            int nJ = rb[J + 1] - rb[J];
+            int local = c - uco[b];
+            int e = h_find(hkeys, hvals, J);
+            if (e < 0 || local < 0 || local >= nJ) {
+                dev_set_error(err, VBARMS_ERR_HIP, lvl, i);
+                continue;
             }
-            // classify entries: keep flag in wst (3 = kept L, 4 = kept U, else discarded)
-            for (int e = t; e < s_n; e += kIlutThreads) {
-                int K = wcol[e];
-                int nK = rb[K + 1] - rb[K];
-                if (K < i) {
-                    wst[e] = wst[e] == 1 ? 3 : 0;
-                } else if (K > i) {
-                    wst[e] = dev_drop<T>(m, nK, w + woff[e], nK, droptol) ? 0 : 4;
-                } else {
-                    wst[e] = 0;
-                }
-            }
-            __syncthreads();
-            for (int e = t; e < s_n; e += kIlutThreads) {
-                int K = wcol[e];
-                int nK = rb[K + 1] - rb[K];
-                if (wst[e] == 3) { atomicAdd(&s_lc, 1); atomicAdd(&s_lw, nK); }
-                if (wst[e] == 4) { atomicAdd(&s_uc, 1); atomicAdd(&s_uw, nK); }
-            }
-            __syncthreads();
-            if (t == 0) {
-                s_lb = atomicAdd((unsigned long long *)&cursors[0], (unsigned long long)s_lc);
-                s_lv = atomicAdd((unsigned long long *)&cursors[1], (unsigned long long)m * s_lw);
-                s_ub = atomicAdd((unsigned long long *)&cursors[2], (unsigned long long)s_uc);
-                s_uv = atomicAdd((unsigned long long *)&cursors[3], (unsigned long long)m * s_uw);
-                if (s_lb + s_lc > capb_pool || s_lv + (int64_t)m * s_lw > capv_pool || s_ub + s_uc > capb_pool ||
-                    s_uv + (int64_t)m * s_uw > capv_pool) {
-                    dev_set_error(err, VBARMS_ERR_OOM, lvl, -1);
-                    __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s_abort = 1;
-                }
-            }
-            __syncthreads();
-            if (!s_abort) {
-                // output position = rank by block column; panel offset = widths of smaller columns
-                for (int e = t; e < s_n; e += kIlutThreads) {
-                    int st = wst[e];
-                    if (st != 3 && st != 4) continue;
-                    int K = wcol[e];
-                    int rank = 0, off = 0;
-                    for (int f = 0; f < s_n; ++f) {
-                        if (wst[f] == st && wcol[f] < K) {
-                            ++rank;
-                            off += rb[wcol[f] + 1] - rb[wcol[f]];
-                        }
-                    }
-                    int nK = rb[K + 1] - rb[K];
-                    const T *src = w + woff[e];
-                    if (st == 3) {
-                        lci[s_lb + rank] = K;
-                        lco[s_lb + rank] = off;
-                        for (int r = 0; r < m; ++r)
-                            for (int c = 0; c < nK; ++c) lv[s_lv + (int64_t)r * s_lw + off + c] = src[r * nK + c];
-                    } else {
-                        uci[s_ub + rank] = K;
-                        uco[s_ub + rank] = off;
-                        for (int r = 0; r < m; ++r)
-                            for (int c = 0; c < nK; ++c) uv[s_uv + (int64_t)r * s_uw + off + c] = src[r * nK + c];
-                    }
-                }
-                if (t == 0) rec[i] = IlutRowRec{s_lb, s_lv, s_ub, s_uv, s_lc, s_lw, s_uc, s_uw};
+            T *wj = w + offs[e] + local;
+            for (int r = 0; r < m; ++r) {
+                T acc = wj[r * nJ];
+                for (int q = 0; q < mk; ++q) acc = acc - M[r * mk + q] * U[q * UW + c];
+                wj[r * nJ] = acc;
             }
         }
-        if (s_abort && t == 0) rec[i] = IlutRowRec{0, 0, 0, 0, 0, 0, 0, 0};
-        __threadfence();
         __syncthreads();
-        if (t == 0) __hip_atomic_store(&done[i], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (t == 0) s_last = k;
+        __syncthreads();
     }
+
+    // finalize row i: pivot block, dropped upper blocks, output to the pools
+    if (t == 0) {
+        s_lc = s_lw = s_uc = s_uw = 0;
+        int ei = h_find(hkeys, hvals, i);
+        T *d = dl + dl_off[i];
+        if (ei < 0) {
+            dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, i);
+            for (int q = 0; q < m * m; ++q) d[q] = T(0);
+            for (int q = 0; q < m; ++q) dl_piv[rb[i] + q] = q;
+        } else {
+            for (int q = 0; q < m * m; ++q) d[q] = w[offs[ei] + q];
+            if (!dev_gepp<T>(m, d, dl_piv + rb[i])) {
+                dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, i);
+                for (int q = 0; q < m; ++q) dl_piv[rb[i] + q] = q;
+            }
+        }
+    }
+    for (int e = t; e < s_nb; e += kIlutThreads) {
+        int K = cols[e];
+        int nK = rb[K + 1] - rb[K];
+        if (K < i) est[e] = est[e] == 1 ? 3 : 0;
+        else if (K > i) est[e] = dev_drop<T>(m, nK, w + offs[e], nK, droptol) ? 0 : 4;
+        else est[e] = 0;
+    }
+    __syncthreads();
+    for (int e = t; e < s_nb; e += kIlutThreads) {
+        int K = cols[e];
+        int nK = rb[K + 1] - rb[K];
+        if (est[e] == 3) { atomicAdd(&s_lc, 1); atomicAdd(&s_lw, nK); }
+        if (est[e] == 4) { atomicAdd(&s_uc, 1); atomicAdd(&s_uw, nK); }
+    }
+    __syncthreads();
+    if (t == 0) {
+        s_lb = (int64_t)atomicAdd((unsigned long long *)&cursors[0], (unsigned long long)s_lc);
+        s_lv = (int64_t)atomicAdd((unsigned long long *)&cursors[1], (unsigned long long)m * s_lw);
+        s_ub = (int64_t)atomicAdd((unsigned long long *)&cursors[2], (unsigned long long)s_uc);
+        s_uv = (int64_t)atomicAdd((unsigned long long *)&cursors[3], (unsigned long long)m * s_uw);
+        if (s_lb + s_lc > capb_pool || s_lv + (int64_t)m * s_lw > capv_pool || s_ub + s_uc > capb_pool ||
+            s_uv + (int64_t)m * s_uw > capv_pool) {
+            dev_set_error(err, VBARMS_ERR_OOM, lvl, -1);
+            s_stop = 1;
+        }
+    }
+    __syncthreads();
+    if (s_stop) return;
+    // output position = rank by block column; panel offset = widths of smaller columns
+    for (int e = t; e < s_nb; e += kIlutThreads) {
+        int st = est[e];
+        if (st != 3 && st != 4) continue;
+        int K = cols[e];
+        int rank = 0, off = 0;
+        for (int f = 0; f < s_nb; ++f) {
+            if (est[f] == st && cols[f] < K) {
+                ++rank;
+                off += rb[cols[f] + 1] - rb[cols[f]];
+            }
+        }
+        int nK = rb[K + 1] - rb[K];
+        const T *src = w + offs[e];
+        if (st == 3) {
+            lci[s_lb + rank] = K;
+            lco[s_lb + rank] = off;
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < nK; ++c) lv[s_lv + (int64_t)r * s_lw + off + c] = src[r * nK + c];
+        } else {
+            uci[s_ub + rank] = K;
+            uco[s_ub + rank] = off;
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < nK; ++c) uv[s_uv + (int64_t)r * s_uw + off + c] = src[r * nK + c];
+        }
+    }
+    if (t == 0) {
+        rec[i] = IlutRowRec{s_lb, s_lv, s_ub, s_uv, s_lc, s_lw, s_uc, s_uw};
+        rs[i] = RowState{s_nb, s_used, s_last, 2};
+        done[i] = launch;
+    }
+}
+
+// next active list: rows of act[] that are not finished
+__global__ void k_unfinished(int nact, const int *act, const RowState *rs, int *flag) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nact) flag[j] = rs[act[j]].status != 2;
+}
+__global__ void k_compact_list(int nact, const int *act, const int *flag, const int *pos, int *out) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nact && flag[j]) out[pos[j]] = act[j];
+}
+
+// capacities of the per-row working rows: `grow` times the input row
+__global__ void k_row_caps(int p, const int *rb, const int64_t *rp, const int64_t *wp, int grow, int64_t *capb,
+                           int64_t *capv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p) return;
+    int64_t nA = rp[i + 1] - rp[i];
+    int64_t m = rb[i + 1] - rb[i];
+    int64_t W = wp[i + 1] - wp[i];
+    capb[i] = std::min<int64_t>(kMaxRowBlocks, std::max<int64_t>(64, grow * nA));
+    capv[i] = std::max<int64_t>(m * 64, grow * m * W);
 }
 
 __global__ void k_rec_counts(int p, const IlutRowRec *rec, int which, int64_t *cnt) {
@@ -312,7 +325,6 @@ __global__ void k_rec_counts(int p, const IlutRowRec *rec, int which, int64_t *c
     if (i >= p) return;
     cnt[i] = which == 0 ? rec[i].lc : rec[i].uc;
 }
-// copy pool rows into ordered block-column lists
 __global__ void k_pool_ci(int p, const IlutRowRec *rec, int which, const int *pci, const int64_t *rp, int *ci) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p) return;
@@ -359,87 +371,70 @@ __global__ void k_sq_sizes(int p, const int *rb, int64_t *sq) {
     if (i < p) sq[i] = (int64_t)(rb[i + 1] - rb[i]) * (rb[i + 1] - rb[i]);
 }
 
-unsigned long long wall_ticks_per_second() {
-    static unsigned long long hz = 0;
-    if (!hz) {
-        int dev = 0, khz = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
-            hz = (unsigned long long)khz * 1000ull;
-        else
-            hz = 100000000ull;
-    }
-    return hz;
-}
-
-// ---- sync-free block substitution ------------------------------------------------------
+// ---- level-scheduled block substitution ---------------------------------------------
 constexpr int kSolveTG = 8;  // lanes per scalar row
 
-// mode 0: t_i = b_i - sum_k L_ik t_k (ascending); mode 1: x_i = D_i^{-1}(t_i - sum_j U_ij x_j)
+// mode 0: t_i = b_i - sum_k L_ik t_k; mode 1: x_i = D_i^{-1}(t_i - sum_j U_ij x_j).
+// One wavefront per block row of the current level; rows of a level are independent.
 template <class T>
-__global__ void __launch_bounds__(256) k_block_trsv(int p, int mode, const int *rb, const int64_t *rp, const int *ci,
+__global__ void __launch_bounds__(256) k_trsv_level(int nrows, const int *rows, int mode, const int *rb,
                                                     const int64_t *wp, const int64_t *vp, const int *sc, const T *v,
                                                     const T *dl, const int64_t *dl_off, const int *dl_piv,
-                                                    const double *b, double *x, int *ticket, int *done, int epoch,
-                                                    int *abort, int *err, unsigned long long limit) {
+                                                    const double *b, double *x) {
     __shared__ double sv[4][VBARMS_MAX_BLOCK];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = blockIdx.x * 4 + wv;
+    if (row >= nrows) return;
+    const int i = rows[row];
+    const int m = rb[i + 1] - rb[i];
+    const int64_t W = wp[i + 1] - wp[i];
     const int grp = lane / kSolveTG, gl = lane % kSolveTG;
-    for (;;) {
-        int tk = 0;
-        if (lane == 0) tk = atomicAdd(ticket, 1);
-        tk = __shfl(tk, 0);
-        if (tk >= p) return;
-        const int i = mode == 0 ? tk : p - 1 - tk;
-        const int m = rb[i + 1] - rb[i];
-        // wait for every row this one reads
-        for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += 64) {
-            int K = ci[k];
-            if (K < 0 || K >= p || (mode == 0 ? K >= i : K <= i)) {
-                dev_set_error(err, VBARMS_ERR_HIP, 3004, i);
-                __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                continue;
-            }
-            wait_flag(&done[K], epoch, abort, err, limit, i);
+    for (int r0 = 0; r0 < m; r0 += 64 / kSolveTG) {
+        const int r = r0 + grp;
+        double acc = 0.0;
+        if (r < m) {
+            const T *a = v + vp[i] + (int64_t)r * W;
+            const int *c = sc + wp[i];
+            for (int64_t j = gl; j < W; j += kSolveTG) acc += (double)a[j] * x[c[j]];
         }
-        __builtin_amdgcn_wave_barrier();  // every lane has seen all its flags
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const int64_t W = wp[i + 1] - wp[i];
-        for (int r0 = 0; r0 < m; r0 += 64 / kSolveTG) {
-            const int r = r0 + grp;
-            double acc = 0.0;
-            if (r < m) {
-                const T *a = v + vp[i] + (int64_t)r * W;
-                const int *c = sc + wp[i];
-                for (int64_t j = gl; j < W; j += kSolveTG) acc += (double)a[j] * x[c[j]];
-            }
 #pragma unroll
-            for (int off = kSolveTG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kSolveTG);
-            if (r < m && gl == 0) sv[wv][r] = b[rb[i] + r] - acc;
+        for (int off = kSolveTG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kSolveTG);
+        if (r < m && gl == 0) sv[wv][r] = b[rb[i] + r] - acc;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) {
+        double *y = sv[wv];
+        if (mode == 1) {
+            const T *d = dl + dl_off[i];
+            dev_lu_fwd<T, double>(m, d, dl_piv + rb[i], y);
+            dev_lu_bwd<T, double>(m, d, y);
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        if (lane == 0) {
-            double *y = sv[wv];
-            if (mode == 1) {
-                const T *d = dl + dl_off[i];
-                dev_lu_fwd<T, double>(m, d, dl_piv + rb[i], y);
-                dev_lu_bwd<T, double>(m, d, y);
-            }
-            for (int r = 0; r < m; ++r) x[rb[i] + r] = y[r];
-            __threadfence();
-            __hip_atomic_store(&done[i], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __builtin_amdgcn_wave_barrier();  // sv[wv] is reused by the next row
+        for (int r = 0; r < m; ++r) x[rb[i] + r] = y[r];
     }
 }
 
-// number of persistent workgroups / wavefronts (tuning knobs; 1 serializes the sweep)
-int env_int(const char *name, int dflt) {
-    const char *v = getenv(name);
-    if (!v || !*v) return dflt;
-    int x = atoi(v);
-    return x > 0 ? x : dflt;
+// level schedule of a triangular block pattern; rows sorted by level, level offsets
+void level_schedule(int p, const std::vector<int64_t> &rp, const std::vector<int> &ci,
+                    bool descending, std::vector<int> &order, std::vector<int> &lptr) {
+    std::vector<int> lev(p, 0);
+    int maxl = -1;
+    for (int s = 0; s < p; ++s) {
+        int i = descending ? p - 1 - s : s;
+        int l = 0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) l = std::max(l, lev[ci[k]] + 1);
+        lev[i] = l;
+        maxl = std::max(maxl, l);
+    }
+    lptr.assign(maxl + 2, 0);
+    for (int i = 0; i < p; ++i) lptr[lev[i] + 1]++;
+    for (int l = 0; l <= maxl; ++l) lptr[l + 1] += lptr[l];
+    order.assign(p, 0);
+    std::vector<int> fill(lptr.begin(), lptr.end() - 1);
+    for (int s = 0; s < p; ++s) {
+        int i = descending ? p - 1 - s : s;
+        order[fill[lev[i]]++] = i;
+    }
 }
 
 }  // namespace
@@ -459,13 +454,11 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
     int64_t dtot = scan_i64(sq.p, last.dl_off.p, p, s);
     last.dl.alloc(std::max<int64_t>(dtot, 1));
     last.dl_piv.alloc(std::max(n, 1));
-    last.done_f.alloc(std::max(p, 1));
-    last.done_b.alloc(std::max(p, 1));
-    fill_i32(last.done_f.p, 0, p, s);
-    fill_i32(last.done_b.p, 0, p, s);
-    last.tickets.alloc(4);
     last.t.alloc(std::max(n, 1));
-    last.epoch = 0;
+    last.lorder.clear();
+    last.uorder.clear();
+    last.lptr.assign(1, 0);
+    last.uptr.assign(1, 0);
     if (p == 0) {
         panel_set_blocks(last.L, A.h_rb, A.h_rb, s);
         panel_set_blocks(last.U, A.h_rb, A.h_rb, s);
@@ -473,76 +466,101 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         last.U.rp.alloc(1); fill_i64(last.U.rp.p, 0, 1, s); panel_finish_layout(last.U, s);
         return;
     }
-    // pools sized generously from the input (fill grows rows); overflow is reported as OOM
-    const int maxm = A.maxm;
     int64_t capb_pool = std::max<int64_t>(4 * A.nb + 1024, 4096);
     int64_t capv_pool = std::max<int64_t>(4 * A.nv + 1024, 65536);
-    int nslot = std::min(p, env_int("VBARMS_ILUT_WORKGROUPS", 1024));
-    // working-row capacity: generous multiple of the largest input row, bounded by the
-    // largest row the LDS list can describe
-    std::vector<int64_t> hvp;
-    to_host(hvp, A.vp.p, p + 1, s);
-    int64_t maxrow = 0;
-    for (int i = 0; i < p; ++i) maxrow = std::max(maxrow, hvp[i + 1] - hvp[i]);
-    int64_t capv = std::min<int64_t>((int64_t)kCapB * maxm * maxm, std::max<int64_t>(65536, 16 * maxrow));
-    for (int attempt = 0; attempt < 3; ++attempt) {
-        DBuf<T> scratch((size_t)nslot * capv);
+    int grow = 8;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        // per-row working rows
+        DBuf<int64_t> capb(p), capv(p), boff(p + 1), voff(p + 1);
+        k_row_caps<<<grid_for(p, 256), 256, 0, s>>>(p, A.rb.p, A.rp.p, A.wp.p, grow, capb.p, capv.p);
+        VB_LAUNCH_CHECK();
+        int64_t totb = scan_i64(capb.p, boff.p, p, s);
+        int64_t totv = scan_i64(capv.p, voff.p, p, s);
+        DBuf<int> wcols(totb), woffs(totb);
+        DBuf<unsigned char> west(totb);
+        DBuf<T> wvals(totv);
+        DBuf<RowState> rs(p);
         DBuf<IlutRowRec> rec(p);
         DBuf<int> lci(capb_pool), lco(capb_pool), uci(capb_pool), uco(capb_pool);
         DBuf<T> lv(capv_pool), uv(capv_pool);
         DBuf<int64_t> cursors(4);
-        DBuf<int> abort(1), done(p);
+        DBuf<int> done(p), act(p), act2(p), flag(p), pos(p + 1);
+        VB_HIP(hipMemsetAsync(rs.p, 0, sizeof(RowState) * p, s));
         fill_i64(cursors.p, 0, 4, s);
-        fill_i32(abort.p, 0, 1, s);
         fill_i32(done.p, 0, p, s);
-        fill_i32(last.tickets.p, 0, 4, s);
+        iota_i32(act.p, p, s);
         VB_HIP(hipMemsetAsync(err, 0, 4 * sizeof(int), s));
-        unsigned long long limit = 20ull * wall_ticks_per_second();
-        k_ilut<T><<<nslot, kIlutThreads, 0, s>>>(p, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p, droptol,
-                                                   last.tickets.p, done.p, 1, abort.p, err, limit, scratch.p, capv,
-                                                   last.dl.p, last.dl_off.p, last.dl_piv.p, rec.p, lci.p, lco.p, lv.p,
-                                                   uci.p, uco.p, uv.p, cursors.p, capb_pool, capv_pool, lvl);
-        VB_LAUNCH_CHECK();
-        std::vector<int> herr;
-        to_host(herr, err, 4, s);
-        if (herr[0] == VBARMS_ERR_OOM && herr[2] == -1 && attempt < 2) {
-            capb_pool *= 3;
-            capv_pool *= 3;
-            continue;  // pools too small: retry with larger pools
+        int nact = p, launch = 0, code = 0, eblock = 0;
+        while (nact > 0) {
+            ++launch;
+            k_ilut_wave<T><<<nact, kIlutThreads, 0, s>>>(
+                launch, p, act.p, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p, droptol, done.p, rs.p, boff.p,
+                voff.p, wcols.p, woffs.p, west.p, wvals.p, last.dl.p, last.dl_off.p, last.dl_piv.p, rec.p, lci.p,
+                lco.p, lv.p, uci.p, uco.p, uv.p, cursors.p, capb_pool, capv_pool, err, lvl);
+            VB_LAUNCH_CHECK();
+            k_unfinished<<<grid_for(nact, 256), 256, 0, s>>>(nact, act.p, rs.p, flag.p);
+            VB_LAUNCH_CHECK();
+            int next = scan_i32(flag.p, pos.p, nact, s);
+            std::vector<int> herr;
+            to_host(herr, err, 4, s);
+            code = herr[0];
+            eblock = herr[2];
+            if (code != 0) break;
+            if (next >= nact) fail(VBARMS_ERR_HIP, "block ILUT made no progress");
+            k_compact_list<<<grid_for(nact, 256), 256, 0, s>>>(nact, act.p, flag.p, pos.p, act2.p);
+            VB_LAUNCH_CHECK();
+            std::swap(act, act2);
+            nact = next;
         }
-        if (herr[0] != 0) return;
+        last.waves = launch;
+        if (code == VBARMS_ERR_OOM && attempt < 3) {
+            // a working row or a pool outgrew its capacity: start again with more room
+            if (eblock == -1) { capb_pool *= 3; capv_pool *= 3; }
+            else grow *= 3;
+            continue;
+        }
+        if (code != 0) return;  // reported by the caller from the error record
         pool_to_panel<T>(p, A.h_rb, A.rb, rec.p, 0, lci.p, lv.p, last.L, s);
         pool_to_panel<T>(p, A.h_rb, A.rb, rec.p, 1, uci.p, uv.p, last.U, s);
-        return;
+        VB_HIP(hipStreamSynchronize(s));
+        break;
     }
+    // level schedules of the two triangular sweeps
+    std::vector<int64_t> rp;
+    std::vector<int> ci;
+    to_host(rp, last.L.rp.p, p + 1, s);
+    to_host(ci, last.L.ci.p, last.L.nb, s);
+    level_schedule(p, rp, ci, false, last.lorder, last.lptr);
+    to_host(rp, last.U.rp.p, p + 1, s);
+    to_host(ci, last.U.ci.p, last.U.nb, s);
+    level_schedule(p, rp, ci, true, last.uorder, last.uptr);
+    last.d_lorder.alloc(p);
+    last.d_uorder.alloc(p);
+    to_device(last.d_lorder.p, last.lorder.data(), p, s);
+    to_device(last.d_uorder.p, last.uorder.data(), p, s);
+    VB_HIP(hipStreamSynchronize(s));
 }
 
 template <class T>
 void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStream_t s) {
+    (void)err;
     const int p = last.A.p;
     if (p == 0) return;
-    ++last.epoch;
-    if (last.epoch == INT_MAX) {
-        fill_i32(last.done_f.p, 0, p, s);
-        fill_i32(last.done_b.p, 0, p, s);
-        last.epoch = 1;
-    }
-    fill_i32(last.tickets.p, 0, 4, s);  // two tickets, tickets[2] = abort flag
-    unsigned long long limit = 10ull * wall_ticks_per_second();
-    // persistent wavefronts, four per workgroup; a wave waits only on rows ticketed before it
-    const int waves = std::min(p, env_int("VBARMS_TRSV_WAVES", 4096));
-    const int threads = waves >= 4 ? 256 : 64 * waves;
-    const unsigned blocks = grid_for((int64_t)waves * 64, threads);
     const Panel<T> &L = last.L, &U = last.U;
-    k_block_trsv<T><<<blocks, threads, 0, s>>>(p, 0, L.rb.p, L.rp.p, L.ci.p, L.wp.p, L.vp.p, L.sc.p, L.v.p,
-                                               last.dl.p, last.dl_off.p, last.dl_piv.p, b, last.t.p, last.tickets.p,
-                                               last.done_f.p, last.epoch, last.tickets.p + 2, err, limit);
-    VB_LAUNCH_CHECK();
-    k_block_trsv<T><<<blocks, threads, 0, s>>>(p, 1, U.rb.p, U.rp.p, U.ci.p, U.wp.p, U.vp.p, U.sc.p, U.v.p,
-                                               last.dl.p, last.dl_off.p, last.dl_piv.p, last.t.p, x,
-                                               last.tickets.p + 1, last.done_b.p, last.epoch, last.tickets.p + 2, err,
-                                               limit);
-    VB_LAUNCH_CHECK();
+    for (size_t l = 0; l + 1 < last.lptr.size(); ++l) {
+        int cnt = last.lptr[l + 1] - last.lptr[l];
+        k_trsv_level<T><<<grid_for(cnt, 4), 256, 0, s>>>(cnt, last.d_lorder.p + last.lptr[l], 0, L.rb.p, L.wp.p,
+                                                          L.vp.p, L.sc.p, L.v.p, last.dl.p, last.dl_off.p,
+                                                          last.dl_piv.p, b, last.t.p);
+        VB_LAUNCH_CHECK();
+    }
+    for (size_t l = 0; l + 1 < last.uptr.size(); ++l) {
+        int cnt = last.uptr[l + 1] - last.uptr[l];
+        k_trsv_level<T><<<grid_for(cnt, 4), 256, 0, s>>>(cnt, last.d_uorder.p + last.uptr[l], 1, U.rb.p, U.wp.p,
+                                                          U.vp.p, U.sc.p, U.v.p, last.dl.p, last.dl_off.p,
+                                                          last.dl_piv.p, last.t.p, x);
+        VB_LAUNCH_CHECK();
+    }
 }
 
 template void factor_last<double>(LastLevel<double> &, double, int, int *, hipStream_t);

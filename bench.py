@@ -1,0 +1,163 @@
+#!/usr/bin/env python3
+"""Time-to-solve benchmark of the VBARMS hot path on one MI355X.
+
+Workload: 40^3 grid, 14-neighbour random stencil, 5 unknowns per node (n = 320,000,
+nnz ~ 21.9M), 10% of each block's entries removed or scaled by 1e-6 so that angle
+compression at tau = 0.8 has to rebuild the blocks; 3 levels, drop tolerance 1e-4,
+FGMRES(50) to a true relative residual of 1e-8, b = A 1.
+
+One step = the whole hot path from the device-resident CSR: compress (Sec. 2.1),
+factor (Sec. 3, all levels and the last-level block ILUT), solve (FGMRES with the
+preconditioner applied every iteration, Alg. 2).  W untimed steps, then K timed steps
+between device synchronizations.  During the timed steps the library records HIP events
+on its own stream around each launch class; the dominant class gives the roofline
+figure.  The oracle (CPU, FP64) solves the same system once on the host for the
+CPU-baseline figure.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solve @1e-8 rel residual + SpMV/solve GB/s, mixed/learned vs FP64 plain"
+HBM_PEAK_GBPS = 8000.0
+TAU, LEVELS, DROPTOL, RESTART, TOL, MAXIT = 0.8, 3, 1e-4, 50, 1e-8, 1000
+
+
+def _cpu_baseline(system):
+    """The oracle, single-threaded, on the same system: compress + factor + FGMRES."""
+    import numpy as np
+    from oracle import oracle as O
+
+    t0 = time.perf_counter()
+    po, bo = O.compress(system.n, system.rowptr, system.col, TAU)
+    orc = O.Oracle(system.n, system.rowptr, system.col, system.val, po, bo, LEVELS, DROPTOL)
+    x, st, its, rel, _ = O.fgmres(system.n, system.rowptr, system.col, system.val, system.b, orc, TOL, RESTART,
+                                  MAXIT)
+    dt = time.perf_counter() - t0
+    return {"value": round(dt, 3), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"the full workload once (one compress + factor + FGMRES solve; status {st}, "
+                      f"{its} iterations, true rel. residual {rel:.2e})"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=("f64", "f32"), default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the whole problem fits on one MI355X and this build has no "
+              "multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1508_02219_amd import synth, vbarms as V
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    system = synth.config_system(2)
+    print(f"[bench] workload {system.name} n={system.n} nnz={system.nnz}", file=sys.stderr, flush=True)
+    rp, ci, va = V.csr_to_device(system)
+    b = torch.as_tensor(system.b, device="cuda")
+    prec = V.F32 if args.precision == "f32" else V.F64
+    sv = V.Solver()
+
+    def step():
+        _, _, st = sv.compress(rp, ci, va, TAU)
+        sv.factor(LEVELS, DROPTOL, 1, prec)
+        x, info = sv.solve(b, tol=TOL, restart=RESTART, maxit=MAXIT)
+        return st, info
+
+    for w in range(args.warmup):
+        print(f"[bench] warmup {w + 1}/{args.warmup}", file=sys.stderr, flush=True)
+        step()
+    sv.set_timing(True)
+    torch.cuda.synchronize()
+    phases = {"compress_ms": 0.0, "factor_ms": 0.0, "solve_ms": 0.0}
+    iters = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st, info = step()
+        if info.status != 0 or info.true_relres > TOL:
+            print(f"[bench] step {k + 1} did not converge: status {info.status} relres {info.true_relres:.3e}",
+                  file=sys.stderr, flush=True)
+            return 1
+        fs = sv.stats()
+        for key in phases:
+            phases[key] += getattr(fs, key)
+        iters.append(info.iters)
+        print(f"[bench] step {k + 1}/{args.steps}: its {info.iters} relres {info.true_relres:.2e} "
+              f"compress {fs.compress_ms:.1f} factor {fs.factor_ms:.1f} solve {fs.solve_ms:.1f} ms",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kst = sv.kernel_stats()
+    sv.set_timing(False)
+    fs = sv.stats()
+    ms_per_step = 1000.0 * elapsed / args.steps
+
+    # dominant launch class by time; its algorithmic bytes per call over its mean call time
+    timed = {k: v for k, v in kst.items() if v[0] > 0}
+    dom = max(timed, key=lambda k: timed[k][1])
+    calls, ms, nbytes = timed[dom]
+    achieved = (nbytes / calls) / (ms / calls * 1e-3) / 1e9 if nbytes > 0 else None
+    roofline = {"bound": "hbm", "kernel": dom, "calls": calls, "avg_us": round(1000.0 * ms / calls, 3),
+                "achieved": None if achieved is None else round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": None if achieved is None else round(achieved / HBM_PEAK_GBPS, 4), "traffic": None}
+    per_class = {k: {"calls": v[0], "ms": round(v[1], 3),
+                     "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 2) if v[1] > 0 and v[2] > 0 else None}
+                 for k, v in kst.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_per_step / 1000.0, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == V.F64 else "f32 factors, f64 krylov",
+        "data": "synthetic",
+        "config": {"workload": "grid40^3 14-neighbour random stencil, 5 unknowns/node, 10% block perturbation",
+                   "n": system.n, "nnz": system.nnz, "tau": TAU, "levels": LEVELS, "droptol": DROPTOL,
+                   "krylov": f"FGMRES({RESTART})", "tol": TOL, "rhs": "A*1"},
+        "phases_ms_mean": {k: round(v / args.steps, 2) for k, v in phases.items()},
+        "iters": iters,
+        "blocks": st.nblocks,
+        "levels_factored": fs.levels,
+        "last_level_supernodes": fs.last_p,
+        "mem_ratio": round(fs.factor_values / max(fs.nnz, 1), 3),
+        "spmv_GBps": per_class["spmv"]["GBps"],
+        "apply_GBps": per_class["apply"]["GBps"],
+        "kernels": per_class,
+        "roofline": roofline,
+    }
+    sv.close()
+    if not args.no_cpu_baseline:
+        print("[bench] oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = _cpu_baseline(system)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -162,6 +162,35 @@ int vbarms_solve(vbarms_t h, const double *b, double *x, double tol, int32_t res
 int vbarms_get_stats(vbarms_t h, vbarms_fstats *st);
 
 /* ---------------------------------------------------------------------------------- */
+/* Kernel timing (measurement support).                                               */
+/* ---------------------------------------------------------------------------------- */
+/* Kernel classes timed with HIP events recorded on the handle's stream around their
+ * launches, together with the algorithmic bytes each launch must move:
+ *   VBARMS_K_SPMV   the FGMRES product A v (one VBSR SpMV launch)
+ *   VBARMS_K_APPLY  one application of M^{-1} (all its launches)
+ *   VBARMS_K_ILUT   one dependency wave of the last-level block ILUT
+ *   VBARMS_K_TRSV   the two last-level block triangular sweeps of one application
+ *   VBARMS_K_ORTHO  one classical Gram-Schmidt pass (dot products and update) */
+#define VBARMS_K_SPMV 0
+#define VBARMS_K_APPLY 1
+#define VBARMS_K_ILUT 2
+#define VBARMS_K_TRSV 3
+#define VBARMS_K_ORTHO 4
+#define VBARMS_K_COUNT 5
+
+typedef struct {
+    int64_t calls;   /* timed launches (or launch groups) */
+    double ms;       /* summed event time, milliseconds */
+    double bytes;    /* summed algorithmic bytes */
+} vbarms_kstat;
+
+/* enable != 0 starts recording (and clears the totals); 0 stops.  Recording adds two
+ * event records per timed launch. */
+int vbarms_set_timing(vbarms_t h, int32_t enable);
+/* out[VBARMS_K_COUNT] (HOST): totals since timing was enabled; synchronizes the stream. */
+int vbarms_kernel_stats(vbarms_t h, vbarms_kstat *out);
+
+/* ---------------------------------------------------------------------------------- */
 /* Inspection of the factors (for verification and analysis).  All outputs are HOST.  */
 /* ---------------------------------------------------------------------------------- */
 /* Matrices that can be exported (block sparse row, dense row-major blocks):

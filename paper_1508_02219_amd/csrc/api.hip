@@ -26,6 +26,7 @@ struct vbarms_ctx {
     vbarms_fstats stats{};
     DBuf<double> wx, wy;        // permuted in/out vectors
     KrylovWork kw;
+    KTimer kt;                  // optional kernel timing
 };
 
 namespace {
@@ -51,14 +52,26 @@ struct Timer {
     }
 };
 
+struct TimerScope {
+    KTimer *prev;
+    explicit TimerScope(KTimer *t) : prev(cur_ktimer()) { cur_ktimer() = t; }
+    ~TimerScope() { cur_ktimer() = prev; }
+};
+
 template <class F>
 int guarded(vbarms_t h, F &&body) {
     if (!h) return VBARMS_ERR_ARG;
     StreamScope scope(h->stream);  // device buffers are allocated and freed on the handle's stream
+    TimerScope tscope(&h->kt);
     try {
         h->last_error.clear();
         VB_HIP(hipSetDevice(h->device));
-        return body();
+        int rc = body();
+        if (!h->kt.pend.empty()) {
+            VB_HIP(hipStreamSynchronize(h->stream));
+            h->kt.resolve();
+        }
+        return rc;
     } catch (const VbError &e) {
         h->last_error = e.msg;
         return e.code;
@@ -151,12 +164,18 @@ void factor_impl(vbarms_t h, const vbarms_fparams *p, std::unique_ptr<Factors<T>
     for (int l = 0; l < VBARMS_MAX_LEVELS; ++l) h->stats.factor_level_ms[l] = l < f.nlev ? f.level_ms[l] : 0.0;
     h->stats.ilut_ms = f.ilut_ms;
     int64_t vals = 0;
+    // bytes of one application: per level the pivot-block factors, G, W and their column
+    // lists, the pivots and about six passes over the level's vectors; then both sweeps
+    double abytes = f.last.sweep_bytes;
     for (int l = 0; l < f.nlev; ++l) {
         const Level<T> &L = f.lev[l];
         std::vector<int64_t> d;
         to_host(d, L.dlu_off.p + L.nis, 1, s);
         vals += d[0] + L.G.nv + L.W.nv;
+        abytes += (double)sizeof(T) * (double)(d[0] + L.G.nv + L.W.nv) + 4.0 * (double)(L.G.nw + L.W.nw) +
+                  4.0 * L.n_is + 8.0 * 6.0 * L.n;
     }
+    f.apply_bytes = abytes;
     {
         std::vector<int64_t> d;
         to_host(d, f.last.dl_off.p + f.last.A.p, 1, s);
@@ -167,8 +186,13 @@ void factor_impl(vbarms_t h, const vbarms_fparams *p, std::unique_ptr<Factors<T>
 
 // M^{-1} in the compressed numbering
 void precond_apply(vbarms_t h, const double *x, double *y) {
-    if (h->precision == VBARMS_F32) solve_levels<float>(*h->f32, 0, x, y, h->err.rec.p, h->stream);
-    else solve_levels<double>(*h->f64, 0, x, y, h->err.rec.p, h->stream);
+    if (h->precision == VBARMS_F32) {
+        KScope ks(VBARMS_K_APPLY, h->f32->apply_bytes, h->stream);
+        solve_levels<float>(*h->f32, 0, x, y, h->err.rec.p, h->stream);
+    } else {
+        KScope ks(VBARMS_K_APPLY, h->f64->apply_bytes, h->stream);
+        solve_levels<double>(*h->f64, 0, x, y, h->err.rec.p, h->stream);
+    }
 }
 
 template <class T>
@@ -415,6 +439,25 @@ int vbarms_get_stats(vbarms_t h, vbarms_fstats *st) {
     if (!h || !st) return VBARMS_ERR_ARG;
     *st = h->stats;
     return VBARMS_OK;
+}
+
+int vbarms_set_timing(vbarms_t h, int32_t enable) {
+    return guarded(h, [&] {
+        VB_HIP(hipStreamSynchronize(h->stream));
+        h->kt.reset();
+        h->kt.on = enable != 0;
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_kernel_stats(vbarms_t h, vbarms_kstat *out) {
+    if (!out) return VBARMS_ERR_ARG;
+    return guarded(h, [&] {
+        VB_HIP(hipStreamSynchronize(h->stream));
+        h->kt.resolve();
+        for (int c = 0; c < VBARMS_K_COUNT; ++c) out[c] = h->kt.tot[c];
+        return VBARMS_OK;
+    });
 }
 
 int vbarms_num_levels(vbarms_t h, int32_t *levels) {

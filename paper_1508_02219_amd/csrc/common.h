@@ -50,6 +50,84 @@ struct StreamScope {
     ~StreamScope() { cur_stream() = prev; }
 };
 
+// ---------------------------------------------------------------------------------
+// Optional timing of kernel classes: a pair of events recorded on the launch stream
+// around each timed launch; the pairs are read after the stream has synchronized.
+// ---------------------------------------------------------------------------------
+struct KTimer {
+    struct Pair {
+        hipEvent_t a, b;
+        int cls;
+        double bytes;
+    };
+    bool on = false;
+    std::vector<Pair> pend;
+    std::vector<hipEvent_t> spare;
+    vbarms_kstat tot[VBARMS_K_COUNT] = {};
+    hipEvent_t take() {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // call only after the stream of every pending pair has synchronized
+    void resolve() {
+        for (const Pair &q : pend) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+                tot[q.cls].calls += 1;
+                tot[q.cls].ms += ms;
+                tot[q.cls].bytes += q.bytes;
+            }
+            spare.push_back(q.a);
+            spare.push_back(q.b);
+        }
+        pend.clear();
+    }
+    void reset() {
+        resolve();
+        for (auto &t : tot) t = vbarms_kstat{};
+    }
+    ~KTimer() {
+        for (const Pair &q : pend) {
+            (void)hipEventDestroy(q.a);
+            (void)hipEventDestroy(q.b);
+        }
+        for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+    }
+};
+inline KTimer *&cur_ktimer() {
+    static thread_local KTimer *t = nullptr;
+    return t;
+}
+// Times the launches enqueued during its lifetime as one call of class `cls`.
+struct KScope {
+    KTimer *t = nullptr;
+    hipEvent_t a = nullptr;
+    hipStream_t s;
+    int cls;
+    double bytes;
+    KScope(int cls_, double bytes_, hipStream_t s_) : s(s_), cls(cls_), bytes(bytes_) {
+        KTimer *k = cur_ktimer();
+        if (k && k->on) {
+            a = k->take();
+            if (a && hipEventRecord(a, s) == hipSuccess) t = k;
+        }
+    }
+    ~KScope() {
+        if (!t) return;
+        hipEvent_t b = t->take();
+        if (b && hipEventRecord(b, s) == hipSuccess) t->pend.push_back(KTimer::Pair{a, b, cls, bytes});
+        else t->spare.push_back(a);
+    }
+    KScope(const KScope &) = delete;
+    KScope &operator=(const KScope &) = delete;
+};
+
 template <class T>
 struct DBuf {
     T *p = nullptr;
@@ -309,5 +387,7 @@ void panel_export(const Panel<T> &a, std::vector<int64_t> &rowptr, std::vector<i
 // SpMV y = A x on the panel (spmv.hip); x indexed by sc, y by scalar row.
 template <class T>
 void panel_spmv(const Panel<T> &a, const double *x, double *y, hipStream_t s);
+template <class T>
+double panel_spmv_bytes(const Panel<T> &a, bool with_b);
 
 }  // namespace vb

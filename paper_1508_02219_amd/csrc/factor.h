@@ -41,6 +41,7 @@ struct LastLevel {
     std::vector<int> uorder, uptr;  // backward sweep
     DBuf<int> d_lorder, d_uorder;   // device copies of the two orders
     int waves = 0;                  // kernel launches the factorization took
+    double sweep_bytes = 0;         // algorithmic bytes of one forward + backward sweep
     DBuf<double> t;               // solve workspace [n]
 };
 
@@ -51,6 +52,7 @@ struct Factors {
     int nlev = 0;
     double level_ms[VBARMS_MAX_LEVELS] = {0};
     double ilut_ms = 0;
+    double apply_bytes = 0;       // algorithmic bytes of one application of M^{-1}
 };
 
 // device error record: {code, level, block, aux}

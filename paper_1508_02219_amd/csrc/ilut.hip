@@ -493,11 +493,14 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         int nact = p, launch = 0, code = 0, eblock = 0;
         while (nact > 0) {
             ++launch;
-            k_ilut_wave<T><<<nact, kIlutThreads, 0, s>>>(
-                launch, p, act.p, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p, droptol, done.p, rs.p, boff.p,
-                voff.p, wcols.p, woffs.p, west.p, wvals.p, last.dl.p, last.dl_off.p, last.dl_piv.p, rec.p, lci.p,
-                lco.p, lv.p, uci.p, uco.p, uv.p, cursors.p, capb_pool, capv_pool, err, lvl);
-            VB_LAUNCH_CHECK();
+            {
+                KScope ks(VBARMS_K_ILUT, 0.0, s);
+                k_ilut_wave<T><<<nact, kIlutThreads, 0, s>>>(
+                    launch, p, act.p, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p, droptol, done.p, rs.p,
+                    boff.p, voff.p, wcols.p, woffs.p, west.p, wvals.p, last.dl.p, last.dl_off.p, last.dl_piv.p, rec.p,
+                    lci.p, lco.p, lv.p, uci.p, uco.p, uv.p, cursors.p, capb_pool, capv_pool, err, lvl);
+                VB_LAUNCH_CHECK();
+            }
             k_unfinished<<<grid_for(nact, 256), 256, 0, s>>>(nact, act.p, rs.p, flag.p);
             VB_LAUNCH_CHECK();
             int next = scan_i32(flag.p, pos.p, nact, s);
@@ -534,6 +537,10 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
     to_host(rp, last.U.rp.p, p + 1, s);
     to_host(ci, last.U.ci.p, last.U.nb, s);
     level_schedule(p, rp, ci, true, last.uorder, last.uptr);
+    // bytes of the two sweeps: L and U values and column lists, the pivot-block LU
+    // factors and pivots, the row offsets, b, t (written and read) and x
+    last.sweep_bytes = (double)sizeof(T) * (double)(last.L.nv + last.U.nv + dtot) + 4.0 * (double)(last.L.nw + last.U.nw) +
+                       2.0 * 20.0 * (p + 1) + 4.0 * n + 8.0 * 4.0 * n + 8.0 * p;
     last.d_lorder.alloc(p);
     last.d_uorder.alloc(p);
     to_device(last.d_lorder.p, last.lorder.data(), p, s);
@@ -547,6 +554,7 @@ void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStr
     const int p = last.A.p;
     if (p == 0) return;
     const Panel<T> &L = last.L, &U = last.U;
+    KScope ks(VBARMS_K_TRSV, last.sweep_bytes, s);
     for (size_t l = 0; l + 1 < last.lptr.size(); ++l) {
         int cnt = last.lptr[l + 1] - last.lptr[l];
         k_trsv_level<T><<<grid_for(cnt, 4), 256, 0, s>>>(cnt, last.d_lorder.p + last.lptr[l], 0, L.rb.p, L.wp.p,

@@ -126,7 +126,10 @@ int fgmres_run(const Panel<double> &A, KrylovWork &kw, const double *b, double *
         status = VBARMS_OK;
     } else {
         for (;;) {
-            panel_spmv_ex<double>(A, x, b, V, s);  // V0 = b - A x
+            {
+                KScope ks(VBARMS_K_SPMV, panel_spmv_bytes(A, true), s);
+                panel_spmv_ex<double>(A, x, b, V, s);  // V0 = b - A x
+            }
             multidot(kw, n, 1, V, V, kw.nrm.p, 0, s);
             k_sqrt_inplace<<<1, 1, 0, s>>>(kw.nrm.p);
             double beta = read_one(kw.nrm.p, s);
@@ -142,14 +145,25 @@ int fgmres_run(const Panel<double> &A, KrylovWork &kw, const double *b, double *
             for (; j < m && it < maxit; ++j) {
                 double *vj = V + (int64_t)j * n, *zj = Z + (int64_t)j * n, *vn = V + (int64_t)(j + 1) * n;
                 precond(vj, zj);
-                panel_spmv<double>(A, zj, vn, s);
+                {
+                    KScope ks(VBARMS_K_SPMV, panel_spmv_bytes(A, false), s);
+                    panel_spmv<double>(A, zj, vn, s);
+                }
                 double *h1 = kw.hdev.p, *h2 = kw.hdev.p + (m + 2);
-                multidot(kw, n, j + 1, V, vn, h1, 0, s);
-                k_update<<<grid_for(n, 256), 256, 0, s>>>(n, j + 1, V, n, h1, vn);
-                VB_LAUNCH_CHECK();
-                multidot(kw, n, j + 1, V, vn, h2, 0, s);
-                k_update<<<grid_for(n, 256), 256, 0, s>>>(n, j + 1, V, n, h2, vn);
-                VB_LAUNCH_CHECK();
+                // one pass reads V_0..V_j twice (dots, update) and w three times
+                const double pass_bytes = 8.0 * (double)n * (2.0 * (j + 1) + 3.0);
+                {
+                    KScope ks(VBARMS_K_ORTHO, pass_bytes, s);
+                    multidot(kw, n, j + 1, V, vn, h1, 0, s);
+                    k_update<<<grid_for(n, 256), 256, 0, s>>>(n, j + 1, V, n, h1, vn);
+                    VB_LAUNCH_CHECK();
+                }
+                {
+                    KScope ks(VBARMS_K_ORTHO, pass_bytes, s);
+                    multidot(kw, n, j + 1, V, vn, h2, 0, s);
+                    k_update<<<grid_for(n, 256), 256, 0, s>>>(n, j + 1, V, n, h2, vn);
+                    VB_LAUNCH_CHECK();
+                }
                 multidot(kw, n, 1, vn, vn, kw.nrm.p, 0, s);
                 k_sqrt_inplace<<<1, 1, 0, s>>>(kw.nrm.p);
                 k_scale_copy<<<grid_for(n, 256), 256, 0, s>>>(n, vn, kw.nrm.p, vn);

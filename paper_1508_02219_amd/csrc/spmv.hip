@@ -44,11 +44,23 @@ void panel_spmv_ex(const Panel<T> &a, const double *x, const double *b, double *
     VB_LAUNCH_CHECK();
 }
 
+// Bytes one product must move: the values, one column index per panel column, the
+// per-block-row offsets (wp, vp, rb), x once, y (and b) once.
+template <class T>
+double panel_spmv_bytes(const Panel<T> &a, bool with_b) {
+    double n = a.h_rb.empty() ? 0.0 : (double)a.h_rb.back();
+    double ncol = a.h_cb.empty() ? 0.0 : (double)a.h_cb.back();
+    return (double)sizeof(T) * (double)a.nv + 4.0 * (double)a.nw + 20.0 * (a.p + 1) + 8.0 * ncol +
+           8.0 * n * (with_b ? 2.0 : 1.0);
+}
+
 template <class T>
 void panel_spmv(const Panel<T> &a, const double *x, double *y, hipStream_t s) {
     panel_spmv_ex<T>(a, x, nullptr, y, s);
 }
 
+template double panel_spmv_bytes<double>(const Panel<double> &, bool);
+template double panel_spmv_bytes<float>(const Panel<float> &, bool);
 template void panel_spmv<double>(const Panel<double> &, const double *, double *, hipStream_t);
 template void panel_spmv<float>(const Panel<float> &, const double *, double *, hipStream_t);
 template void panel_spmv_ex<double>(const Panel<double> &, const double *, const double *, double *, hipStream_t);

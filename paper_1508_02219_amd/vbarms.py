@@ -22,6 +22,10 @@ MAX_LEVELS = 16
 MAX_BLOCK = 32
 # exportable matrices
 M_A, M_AS, M_G, M_W, M_D, M_LAST, M_L, M_U, M_DL = range(9)
+# timed kernel classes
+K_SPMV, K_APPLY, K_ILUT, K_TRSV, K_ORTHO = range(5)
+K_COUNT = 5
+K_NAMES = ("spmv", "apply", "ilut_wave", "trsv_sweeps", "cgs_pass")
 
 _ERRNAMES = {ERR_ARG: "ERR_ARG", ERR_HIP: "ERR_HIP", ERR_OOM: "ERR_OOM", ERR_SINGULAR: "ERR_SINGULAR",
              ERR_NAN: "ERR_NAN", ERR_STATE: "ERR_STATE"}
@@ -58,6 +62,10 @@ class FStats(C.Structure):
                 ("last_p", C.c_int32), ("factor_values", C.c_int64), ("nnz", C.c_int64)]
 
 
+class KStat(C.Structure):
+    _fields_ = [("calls", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double)]
+
+
 # name -> (restype, argtypes)
 _P = C.c_void_p
 SIGNATURES = {
@@ -72,6 +80,8 @@ SIGNATURES = {
     "vbarms_spmv": (C.c_int, [_P, _P, _P]),
     "vbarms_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, C.c_int32, C.POINTER(SInfo)]),
     "vbarms_get_stats": (C.c_int, [_P, C.POINTER(FStats)]),
+    "vbarms_set_timing": (C.c_int, [_P, C.c_int32]),
+    "vbarms_kernel_stats": (C.c_int, [_P, C.POINTER(KStat)]),
     "vbarms_num_levels": (C.c_int, [_P, _P]),
     "vbarms_level_info": (C.c_int, [_P, C.c_int32, _P]),
     "vbarms_level_is": (C.c_int, [_P, C.c_int32, _P]),
@@ -231,6 +241,16 @@ class Solver:
         st = FStats()
         self._check(lib().vbarms_get_stats(self.h, C.byref(st)))
         return st
+
+    def set_timing(self, enable=True):
+        """Starts (and clears) or stops event timing of the kernel classes K_*."""
+        self._check(lib().vbarms_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_stats(self):
+        """{name: (calls, total ms, total algorithmic bytes)} since timing was enabled."""
+        out = (KStat * K_COUNT)()
+        self._check(lib().vbarms_kernel_stats(self.h, out))
+        return {K_NAMES[c]: (int(out[c].calls), float(out[c].ms), float(out[c].bytes)) for c in range(K_COUNT)}
 
     # -- inspection -----------------------------------------------------------------------
     def num_levels(self):

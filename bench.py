@@ -56,6 +56,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=("f64", "f32"), default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three 1 GiB device-to-device copies (the reference for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the whole problem fits on one MI355X and this build has no "
@@ -71,6 +73,15 @@ def main() -> int:
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy of known size: each copy reads and writes exactly 1 GiB
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}), flush=True)
+        return 0
     system = synth.config_system(2)
     print(f"[bench] workload {system.name} n={system.n} nnz={system.nnz}", file=sys.stderr, flush=True)
     rp, ci, va = V.csr_to_device(system)

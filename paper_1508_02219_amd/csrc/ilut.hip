@@ -24,6 +24,9 @@ namespace {
 constexpr int kIlutThreads = 256;
 constexpr int kHashCap = 2048;  // LDS hash slots: at most kMaxRowBlocks entries
 constexpr int kMaxRowBlocks = 1024;
+constexpr int kMaxM = VBARMS_MAX_BLOCK;
+constexpr int kUStage = 2048;   // values of U row k staged in LDS when they fit
+constexpr int kCheckEvery = 8;  // ILUT waves between host checks
 
 struct IlutRowRec {
     int64_t lb, lv, ub, uv;  // block / value offsets in the pools
@@ -51,26 +54,46 @@ __device__ inline void h_insert(int *keys, int *vals, int key, int val) {
     }
 }
 
-// One wave of the block ILUT: one workgroup per unfinished row in act[].
+// One dependency wave of the block ILUT: one workgroup per row of the input list.
+//
+// The row's block list (column, value offset, state) lives in LDS for the launch and in
+// its global region between launches; the dense blocks stay in the global region.  The
+// pivot-block LU of row k, the multiplier block and U row k are staged in LDS before the
+// small dense solves, which keep the operation order of the sequential algorithm.  A row
+// that meets an unfinished row k saves its list and appends itself to the output list.
+//
+// Counters rotate over three slots: launch L reads cnt_in, appends to cnt_out and clears
+// cnt_clear, which launch L-1 read and launch L+1 will append to.
 template <class T>
 __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
-    int launch, int p, const int *act, const int *rb, const int64_t *rp, const int *ci, const int *co, const int64_t *wp,
-    const int64_t *vp, const T *av, double droptol, int *done, RowState *rs, const int64_t *boff, const int64_t *voff,
-    int *wcols, int *woffs, unsigned char *west, T *wvals, T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec,
-    int *lci, int *lco, T *lv, int *uci, int *uco, T *uv, int64_t *cursors, int64_t capb_pool, int64_t capv_pool,
-    int *err, int lvl) {
+    int launch, int p, const int *act_in, const int *cnt_in, int *act_out, int *cnt_out, int *cnt_clear,
+    const int *rb, const int64_t *rp, const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av,
+    double droptol, int *done, RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols, int *woffs,
+    unsigned char *west, T *wvals, T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec, int *lci, int *lco,
+    T *lv, int *uci, int *uco, T *uv, int64_t *cursors, int64_t capb_pool, int64_t capv_pool, int *err, int lvl,
+    unsigned long long *moved) {
     __shared__ int hkeys[kHashCap], hvals[kHashCap];
-    __shared__ int s_nb, s_used, s_last, s_status, s_min, s_flag, s_stop;
+    __shared__ int l_cols[kMaxRowBlocks], l_offs[kMaxRowBlocks];
+    __shared__ unsigned char l_est[kMaxRowBlocks];  // 0 pending, 1 eliminated, 2 dropped (3/4: kept L/U)
+    __shared__ T s_lu[kMaxM * kMaxM], s_M[kMaxM * kMaxM], s_U[kUStage];
+    __shared__ int s_piv[kMaxM];
+    __shared__ int s_nb, s_used, s_last, s_status, s_min, s_flag, s_stop, s_ek;
+    __shared__ IlutRowRec s_rk;
     __shared__ int s_lc, s_lw, s_uc, s_uw;
     __shared__ int64_t s_lb, s_lv, s_ub, s_uv;
     const int t = threadIdx.x;
-    const int i = act[blockIdx.x];
+    if (blockIdx.x == 0 && t == 0) *cnt_clear = 0;
+    if ((int)blockIdx.x >= *cnt_in) return;
+    constexpr int S = (int)sizeof(T);
+    // algorithmic bytes of the work this row does in this launch (thread 0 keeps the sum)
+    unsigned long long nbytes = 0;
+    const int i = act_in[blockIdx.x];
     const int m = rb[i + 1] - rb[i];
     const int64_t B0 = boff[i], CB = boff[i + 1] - boff[i];
     const int64_t V0 = voff[i], CV = voff[i + 1] - voff[i];
     int *cols = wcols + B0;
     int *offs = woffs + B0;
-    unsigned char *est = west + B0;  // 0 pending, 1 eliminated, 2 dropped (3/4 at output: kept L/U)
+    unsigned char *est = west + B0;
     T *w = wvals + V0;
     if (t == 0) {
         RowState r = rs[i];
@@ -89,17 +112,20 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
             s_nb = nA;
             s_used = (int)(m * W);
             s_last = -1;
+            nbytes += 2ull * S * m * W + 8ull * nA;  // row of A in, working row out
+        } else {
+            nbytes += 9ull * r.nb;  // saved block list back in
         }
     }
     __syncthreads();
     if (s_stop) return;
     if (s_status == 0) {
-        // first visit: row i of A, one entry per block, blocks stored contiguously
+        // first visit: row i of A, one list entry per block, blocks stored contiguously
         const int64_t b0 = rp[i];
         for (int e = t; e < s_nb; e += kIlutThreads) {
-            cols[e] = ci[b0 + e];
-            offs[e] = m * co[b0 + e];
-            est[e] = 0;
+            l_cols[e] = ci[b0 + e];
+            l_offs[e] = m * co[b0 + e];
+            l_est[e] = 0;
         }
         const int64_t W = wp[i + 1] - wp[i];
         const T *A = av + vp[i];
@@ -110,24 +136,30 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
             int off = m * co[b];
             for (int r = 0; r < m; ++r) w[off + r * nJ + local] = A[r * W + c];
         }
+    } else {
+        for (int e = t; e < s_nb; e += kIlutThreads) {
+            l_cols[e] = cols[e];
+            l_offs[e] = offs[e];
+            l_est[e] = est[e];
+        }
     }
     for (int h = t; h < kHashCap; h += kIlutThreads) hkeys[h] = -1;
     __syncthreads();
-    for (int e = t; e < s_nb; e += kIlutThreads) h_insert(hkeys, hvals, cols[e], e);
+    for (int e = t; e < s_nb; e += kIlutThreads) h_insert(hkeys, hvals, l_cols[e], e);
     __syncthreads();
 
     for (;;) {
         if (t == 0) s_min = INT_MAX;
         __syncthreads();
         for (int e = t; e < s_nb; e += kIlutThreads) {
-            int K = cols[e];
-            if (K < i && K > s_last && est[e] == 0) atomicMin(&s_min, K);
+            int K = l_cols[e];
+            if (K < i && K > s_last && l_est[e] == 0) atomicMin(&s_min, K);
         }
         __syncthreads();
         const int k = s_min;
         if (k == INT_MAX) break;
         if (t == 0) {
-            // row k is usable only if it was finished by an earlier launch
+            // row k is usable only if an earlier launch finished it
             const int dk = done[k];
             s_flag = (dk > 0 && dk < launch) ? 1 : 0;
             if (s_flag) {
@@ -141,35 +173,70 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
                     dev_set_error(err, VBARMS_ERR_HIP, lvl, i);
                     s_flag = 2;
                 }
+                s_ek = e0;
+                s_rk = r;
             }
         }
         __syncthreads();
         if (s_flag != 1) {
-            // not finished yet: keep the state and resume in the next launch
-            if (t == 0 && s_flag == 0) rs[i] = RowState{s_nb, s_used, s_last, 1};
+            if (s_flag == 0) {
+                // not finished yet: save the list and state, queue the row for the next launch
+                for (int e = t; e < s_nb; e += kIlutThreads) {
+                    cols[e] = l_cols[e];
+                    offs[e] = l_offs[e];
+                    est[e] = l_est[e];
+                }
+                if (t == 0) {
+                    rs[i] = RowState{s_nb, s_used, s_last, 1};
+                    act_out[atomicAdd(cnt_out, 1)] = i;
+                    nbytes += 9ull * s_nb + 24;
+                }
+            }
+            if (t == 0) atomicAdd(moved, nbytes);
             return;
         }
-        const int ek = h_find(hkeys, hvals, k);
+        const int ek = s_ek;
         const int mk = rb[k + 1] - rb[k];
-        const IlutRowRec rk = rec[k];
-        T *M = w + offs[ek];
-        const T *dk_lu = dl + dl_off[k];
-        if (t < m) {
-            dev_row_solve_u<T>(mk, dk_lu, M + t * mk, 1);
-            dev_row_solve_lp<T>(mk, dk_lu, dl_piv + rb[k], M + t * mk, 1);
+        const IlutRowRec rk = s_rk;
+        const int UW = rk.uw;
+        const bool ustaged = (int64_t)mk * UW <= kUStage;
+        // stage the pivot-block LU of row k, its pivots, the multiplier block and U row k
+        {
+            const T *dk = dl + dl_off[k];
+            for (int e = t; e < mk * mk; e += kIlutThreads) s_lu[e] = dk[e];
+            for (int q = t; q < mk; q += kIlutThreads) s_piv[q] = dl_piv[rb[k] + q];
+            const T *Mg = w + l_offs[ek];
+            for (int e = t; e < m * mk; e += kIlutThreads) s_M[e] = Mg[e];
+            if (ustaged)
+                for (int e = t; e < mk * UW; e += kIlutThreads) s_U[e] = uv[rk.uv + e];
         }
         __syncthreads();
-        if (t == 0) s_flag = dev_drop<T>(m, mk, M, mk, droptol);
+        if (t < m) {
+            dev_row_solve_u<T>(mk, s_lu, s_M + t * mk, 1);
+            dev_row_solve_lp<T>(mk, s_lu, s_piv, s_M + t * mk, 1);
+        }
+        __syncthreads();
+        if (t == 0) {
+            s_flag = dev_drop<T>(m, mk, s_M, mk, droptol);
+            // readiness and record of row k, its pivot block, the multiplier in and out
+            nbytes += 68ull + (unsigned long long)S * mk * mk + 4ull * mk + 2ull * S * m * mk;
+            // U row k with its block lists, and the read-modify-write of the updated blocks
+            if (!s_flag) nbytes += (unsigned long long)S * mk * UW + 8ull * rk.uc + 2ull * S * m * UW;
+        }
         __syncthreads();
         if (s_flag) {
             if (t == 0) {
-                est[ek] = 2;
+                l_est[ek] = 2;
                 s_last = k;
             }
             __syncthreads();
             continue;
         }
-        if (t == 0) est[ek] = 1;
+        {
+            T *Mg = w + l_offs[ek];
+            for (int e = t; e < m * mk; e += kIlutThreads) Mg[e] = s_M[e];
+        }
+        if (t == 0) l_est[ek] = 1;
         // fill: blocks of U row k not yet in the working row
         for (int b = t; b < rk.uc; b += kIlutThreads) {
             int J = uci[rk.ub + b];
@@ -187,17 +254,15 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
                 s_stop = 1;
                 continue;
             }
-            cols[e] = J;
-            offs[e] = off;
-            est[e] = 0;
+            l_cols[e] = J;
+            l_offs[e] = off;
+            l_est[e] = 0;
             for (int q = 0; q < m * nJ; ++q) w[off + q] = T(0);
             h_insert(hkeys, hvals, J, e);
         }
         __syncthreads();
         if (s_stop) return;
         // w_J -= M U_kJ for every block J of U row k
-        const T *U = uv + rk.uv;
-        const int UW = rk.uw;
         for (int c = t; c < UW; c += kIlutThreads) {
             int64_t b = dev_floor32(uco, rk.ub, rk.ub + rk.uc, c);
             int J = uci[b];
@@ -208,10 +273,11 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
                 dev_set_error(err, VBARMS_ERR_HIP, lvl, i);
                 continue;
             }
-            T *wj = w + offs[e] + local;
+            T *wj = w + l_offs[e] + local;
+            const T *Ug = uv + rk.uv + c;
             for (int r = 0; r < m; ++r) {
                 T acc = wj[r * nJ];
-                for (int q = 0; q < mk; ++q) acc = acc - M[r * mk + q] * U[q * UW + c];
+                for (int q = 0; q < mk; ++q) acc = acc - s_M[r * mk + q] * (ustaged ? s_U[q * UW + c] : Ug[(int64_t)q * UW]);
                 wj[r * nJ] = acc;
             }
         }
@@ -221,35 +287,40 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
     }
 
     // finalize row i: pivot block, dropped upper blocks, output to the pools
+    const int ei = h_find(hkeys, hvals, i);
+    if (ei >= 0)
+        for (int e = t; e < m * m; e += kIlutThreads) s_M[e] = w[l_offs[ei] + e];
+    __syncthreads();
     if (t == 0) {
         s_lc = s_lw = s_uc = s_uw = 0;
-        int ei = h_find(hkeys, hvals, i);
-        T *d = dl + dl_off[i];
         if (ei < 0) {
             dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, i);
-            for (int q = 0; q < m * m; ++q) d[q] = T(0);
-            for (int q = 0; q < m; ++q) dl_piv[rb[i] + q] = q;
-        } else {
-            for (int q = 0; q < m * m; ++q) d[q] = w[offs[ei] + q];
-            if (!dev_gepp<T>(m, d, dl_piv + rb[i])) {
-                dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, i);
-                for (int q = 0; q < m; ++q) dl_piv[rb[i] + q] = q;
-            }
+            for (int q = 0; q < m * m; ++q) s_M[q] = T(0);
+            for (int q = 0; q < m; ++q) s_piv[q] = q;
+        } else if (!dev_gepp<T>(m, s_M, s_piv)) {
+            dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, i);
+            for (int q = 0; q < m; ++q) s_piv[q] = q;
         }
     }
+    __syncthreads();
+    {
+        T *d = dl + dl_off[i];
+        for (int e = t; e < m * m; e += kIlutThreads) d[e] = s_M[e];
+        for (int q = t; q < m; q += kIlutThreads) dl_piv[rb[i] + q] = s_piv[q];
+    }
     for (int e = t; e < s_nb; e += kIlutThreads) {
-        int K = cols[e];
+        int K = l_cols[e];
         int nK = rb[K + 1] - rb[K];
-        if (K < i) est[e] = est[e] == 1 ? 3 : 0;
-        else if (K > i) est[e] = dev_drop<T>(m, nK, w + offs[e], nK, droptol) ? 0 : 4;
-        else est[e] = 0;
+        if (K < i) l_est[e] = l_est[e] == 1 ? 3 : 0;
+        else if (K > i) l_est[e] = dev_drop<T>(m, nK, w + l_offs[e], nK, droptol) ? 0 : 4;
+        else l_est[e] = 0;
     }
     __syncthreads();
     for (int e = t; e < s_nb; e += kIlutThreads) {
-        int K = cols[e];
+        int K = l_cols[e];
         int nK = rb[K + 1] - rb[K];
-        if (est[e] == 3) { atomicAdd(&s_lc, 1); atomicAdd(&s_lw, nK); }
-        if (est[e] == 4) { atomicAdd(&s_uc, 1); atomicAdd(&s_uw, nK); }
+        if (l_est[e] == 3) { atomicAdd(&s_lc, 1); atomicAdd(&s_lw, nK); }
+        if (l_est[e] == 4) { atomicAdd(&s_uc, 1); atomicAdd(&s_uw, nK); }
     }
     __syncthreads();
     if (t == 0) {
@@ -267,18 +338,18 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
     if (s_stop) return;
     // output position = rank by block column; panel offset = widths of smaller columns
     for (int e = t; e < s_nb; e += kIlutThreads) {
-        int st = est[e];
+        int st = l_est[e];
         if (st != 3 && st != 4) continue;
-        int K = cols[e];
+        int K = l_cols[e];
         int rank = 0, off = 0;
         for (int f = 0; f < s_nb; ++f) {
-            if (est[f] == st && cols[f] < K) {
+            if (l_est[f] == st && l_cols[f] < K) {
                 ++rank;
-                off += rb[cols[f] + 1] - rb[cols[f]];
+                off += rb[l_cols[f] + 1] - rb[l_cols[f]];
             }
         }
         int nK = rb[K + 1] - rb[K];
-        const T *src = w + offs[e];
+        const T *src = w + l_offs[e];
         if (st == 3) {
             lci[s_lb + rank] = K;
             lco[s_lb + rank] = off;
@@ -295,17 +366,10 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
         rec[i] = IlutRowRec{s_lb, s_lv, s_ub, s_uv, s_lc, s_lw, s_uc, s_uw};
         rs[i] = RowState{s_nb, s_used, s_last, 2};
         done[i] = launch;
+        // pivot block in and its LU out, kept blocks copied to the pools, the records
+        nbytes += 2ull * S * m * m + 4ull * m + 2ull * S * m * (s_lw + s_uw) + 8ull * (s_lc + s_uc) + 72;
+        atomicAdd(moved, nbytes);
     }
-}
-
-// next active list: rows of act[] that are not finished
-__global__ void k_unfinished(int nact, const int *act, const RowState *rs, int *flag) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < nact) flag[j] = rs[act[j]].status != 2;
-}
-__global__ void k_compact_list(int nact, const int *act, const int *flag, const int *pos, int *out) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < nact && flag[j]) out[pos[j]] = act[j];
 }
 
 // capacities of the per-row working rows: `grow` times the input row
@@ -376,18 +440,26 @@ constexpr int kSolveTG = 8;  // lanes per scalar row
 
 // mode 0: t_i = b_i - sum_k L_ik t_k; mode 1: x_i = D_i^{-1}(t_i - sum_j U_ij x_j).
 // One wavefront per block row of the current level; rows of a level are independent.
+// The pivot-block LU factors and pivots are staged in LDS before the small solve.
 template <class T>
 __global__ void __launch_bounds__(256) k_trsv_level(int nrows, const int *rows, int mode, const int *rb,
                                                     const int64_t *wp, const int64_t *vp, const int *sc, const T *v,
                                                     const T *dl, const int64_t *dl_off, const int *dl_piv,
                                                     const double *b, double *x) {
     __shared__ double sv[4][VBARMS_MAX_BLOCK];
+    __shared__ T slu[4][VBARMS_MAX_BLOCK * VBARMS_MAX_BLOCK];
+    __shared__ int spiv[4][VBARMS_MAX_BLOCK];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = blockIdx.x * 4 + wv;
     if (row >= nrows) return;
     const int i = rows[row];
     const int m = rb[i + 1] - rb[i];
     const int64_t W = wp[i + 1] - wp[i];
+    if (mode == 1) {
+        const T *d = dl + dl_off[i];
+        for (int e = lane; e < m * m; e += 64) slu[wv][e] = d[e];
+        if (lane < m) spiv[wv][lane] = dl_piv[rb[i] + lane];
+    }
     const int grp = lane / kSolveTG, gl = lane % kSolveTG;
     for (int r0 = 0; r0 < m; r0 += 64 / kSolveTG) {
         const int r = r0 + grp;
@@ -403,15 +475,20 @@ __global__ void __launch_bounds__(256) k_trsv_level(int nrows, const int *rows, 
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     if (lane == 0) {
         double *y = sv[wv];
         if (mode == 1) {
-            const T *d = dl + dl_off[i];
-            dev_lu_fwd<T, double>(m, d, dl_piv + rb[i], y);
-            dev_lu_bwd<T, double>(m, d, y);
+            dev_lu_fwd<T, double>(m, slu[wv], spiv[wv], y);
+            dev_lu_bwd<T, double>(m, slu[wv], y);
         }
-        for (int r = 0; r < m; ++r) x[rb[i] + r] = y[r];
     }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lane < m) x[rb[i] + lane] = sv[wv][lane];
 }
 
 // level schedule of a triangular block pattern; rows sorted by level, level offsets
@@ -484,38 +561,49 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         DBuf<int> lci(capb_pool), lco(capb_pool), uci(capb_pool), uco(capb_pool);
         DBuf<T> lv(capv_pool), uv(capv_pool);
         DBuf<int64_t> cursors(4);
-        DBuf<int> done(p), act(p), act2(p), flag(p), pos(p + 1);
+        DBuf<int> done(p), lists(2 * (size_t)p), cnt(3);
+        DBuf<unsigned long long> moved(1);
+        fill_val<unsigned long long>(moved.p, 0ull, 1, s);
         VB_HIP(hipMemsetAsync(rs.p, 0, sizeof(RowState) * p, s));
         fill_i64(cursors.p, 0, 4, s);
         fill_i32(done.p, 0, p, s);
-        iota_i32(act.p, p, s);
+        iota_i32(lists.p + p, p, s);  // list of launch 1 (odd launches read the second list)
+        const int cnt0[3] = {0, p, 0};
+        to_device(cnt.p, cnt0, 3, s);
         VB_HIP(hipMemsetAsync(err, 0, 4 * sizeof(int), s));
-        int nact = p, launch = 0, code = 0, eblock = 0;
-        while (nact > 0) {
-            ++launch;
-            {
+        int known = p, launch = 0, code = 0, eblock = 0;
+        while (known > 0) {
+            // every launch finishes at least one row (the smallest unfinished one), so the
+            // list shrinks by at least kCheckEvery between checks until it is empty
+            if (launch > p + kCheckEvery) fail(VBARMS_ERR_HIP, "block ILUT made no progress");
+            for (int q = 0; q < kCheckEvery; ++q) {
+                ++launch;
+                const int *in_l = lists.p + (size_t)(launch & 1) * p;
+                int *out_l = lists.p + (size_t)((launch + 1) & 1) * p;
                 KScope ks(VBARMS_K_ILUT, 0.0, s);
-                k_ilut_wave<T><<<nact, kIlutThreads, 0, s>>>(
-                    launch, p, act.p, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p, droptol, done.p, rs.p,
-                    boff.p, voff.p, wcols.p, woffs.p, west.p, wvals.p, last.dl.p, last.dl_off.p, last.dl_piv.p, rec.p,
-                    lci.p, lco.p, lv.p, uci.p, uco.p, uv.p, cursors.p, capb_pool, capv_pool, err, lvl);
+                k_ilut_wave<T><<<known, kIlutThreads, 0, s>>>(
+                    launch, p, in_l, cnt.p + launch % 3, out_l, cnt.p + (launch + 1) % 3, cnt.p + (launch + 2) % 3,
+                    A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p, droptol, done.p, rs.p, boff.p, voff.p,
+                    wcols.p, woffs.p, west.p, wvals.p, last.dl.p, last.dl_off.p, last.dl_piv.p, rec.p, lci.p, lco.p,
+                    lv.p, uci.p, uco.p, uv.p, cursors.p, capb_pool, capv_pool, err, lvl, moved.p);
                 VB_LAUNCH_CHECK();
             }
-            k_unfinished<<<grid_for(nact, 256), 256, 0, s>>>(nact, act.p, rs.p, flag.p);
-            VB_LAUNCH_CHECK();
-            int next = scan_i32(flag.p, pos.p, nact, s);
-            std::vector<int> herr;
+            std::vector<int> hc, herr;
+            to_host(hc, cnt.p, 3, s);
             to_host(herr, err, 4, s);
             code = herr[0];
             eblock = herr[2];
             if (code != 0) break;
-            if (next >= nact) fail(VBARMS_ERR_HIP, "block ILUT made no progress");
-            k_compact_list<<<grid_for(nact, 256), 256, 0, s>>>(nact, act.p, flag.p, pos.p, act2.p);
-            VB_LAUNCH_CHECK();
-            std::swap(act, act2);
-            nact = next;
+            const int next = hc[(launch + 1) % 3];
+            if (next > 0 && next > known - kCheckEvery) fail(VBARMS_ERR_HIP, "block ILUT made no progress");
+            known = next;
         }
         last.waves = launch;
+        {
+            // the bytes the waves moved, credited to the ILUT timing class
+            KTimer *kt = cur_ktimer();
+            if (kt && kt->on) kt->tot[VBARMS_K_ILUT].bytes += (double)read_one(moved.p, s);
+        }
         if (code == VBARMS_ERR_OOM && attempt < 3) {
             // a working row or a pool outgrew its capacity: start again with more room
             if (eblock == -1) { capb_pool *= 3; capv_pool *= 3; }

@@ -274,3 +274,35 @@ def test_zero_rhs_and_repeated_calls(vb):
     y1 = sv.apply(b)
     y2 = sv.apply(b)
     assert torch.equal(y1, y2)
+
+
+def test_ilut_capacity_retry_matches_oracle(vb, orc):
+    # zero dropping on a random pattern makes last-level rows fill far beyond the room
+    # first reserved for them, so the factorization restarts with larger working rows
+    s = synth.random_pattern_matrix(120, 0.05, twins=0, seed=401, diag=20.0)
+    o, sv, A, st, err = _run_both(vb, orc, s, 1.0, 0, 0.0)
+    assert err is None and o.status == 0, err
+    _check_all_factors(vb, orc, o, sv)
+
+
+def test_kernel_timing_counts_launches(vb, orc):
+    import torch
+    s = synth.grid_system(5, 5, 4, ell=4, stencil="14rand", perturb=0.1, seed=77)
+    o, sv, A, st, err = _run_both(vb, orc, s, 0.8, 2, 1e-3)
+    assert err is None
+    sv.set_timing(True)
+    x, info = sv.solve(torch.as_tensor(s.b, device="cuda"), tol=1e-8, restart=20)
+    ks = sv.kernel_stats()
+    sv.set_timing(False)
+    assert info.status == 0
+    # one preconditioner application and one product per Arnoldi step, plus one residual
+    # product per restart cycle (and the final check)
+    assert ks["apply"][0] == info.iters
+    assert ks["spmv"][0] == info.iters + info.restarts + 1
+    assert ks["cgs_pass"][0] == 2 * info.iters
+    assert ks["trsv_sweeps"][0] == info.iters
+    for name in ("apply", "spmv", "cgs_pass", "trsv_sweeps"):
+        calls, ms, nbytes = ks[name]
+        assert ms > 0 and nbytes > 0, name
+    sv.set_timing(True)  # clears
+    assert all(v[0] == 0 for v in sv.kernel_stats().values())

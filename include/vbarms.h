@@ -161,6 +161,12 @@ int vbarms_solve(vbarms_t h, const double *b, double *x, double tol, int32_t res
 /* Timings and sizes of the last compress / factor / solve on this handle (HOST). */
 int vbarms_get_stats(vbarms_t h, vbarms_fstats *st);
 
+/* enable != 0 (the default) replays the level launches of the last-level triangular
+ * sweeps from a HIP graph captured at the first application after each factorization;
+ * 0 launches them one by one.  Both give identical results.  Takes effect at the next
+ * application. */
+int vbarms_set_graphs(vbarms_t h, int32_t enable);
+
 /* ---------------------------------------------------------------------------------- */
 /* Kernel timing (measurement support).                                               */
 /* ---------------------------------------------------------------------------------- */

@@ -27,6 +27,7 @@ struct vbarms_ctx {
     DBuf<double> wx, wy;        // permuted in/out vectors
     KrylovWork kw;
     KTimer kt;                  // optional kernel timing
+    bool graphs = true;         // replay the last-level sweeps from a captured graph
 };
 
 namespace {
@@ -155,6 +156,7 @@ void factor_impl(vbarms_t h, const vbarms_fparams *p, std::unique_ptr<Factors<T>
         if (f.lev[l].nis == 0) break;
     }
     f.last.A = std::move(cur);
+    f.last.use_graph = h->graphs;
     Timer tm(s);
     factor_last<T>(f.last, p->droptol[levels], f.nlev, h->err.rec.p, s);
     check_dev_err(h, "last-level ILUT");
@@ -439,6 +441,15 @@ int vbarms_get_stats(vbarms_t h, vbarms_fstats *st) {
     if (!h || !st) return VBARMS_ERR_ARG;
     *st = h->stats;
     return VBARMS_OK;
+}
+
+int vbarms_set_graphs(vbarms_t h, int32_t enable) {
+    return guarded(h, [&] {
+        h->graphs = enable != 0;
+        if (h->f64) h->f64->last.use_graph = h->graphs;
+        if (h->f32) h->f32->last.use_graph = h->graphs;
+        return VBARMS_OK;
+    });
 }
 
 int vbarms_set_timing(vbarms_t h, int32_t enable) {

@@ -29,6 +29,22 @@ struct Level {
     DBuf<double> g, z;            // apply workspace [n_rest]: next level's right-hand side / solution
 };
 
+// An instantiated graph of captured launches (owned; destroyed with its owner).
+struct LaunchGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    LaunchGraph() = default;
+    LaunchGraph(const LaunchGraph &) = delete;
+    LaunchGraph &operator=(const LaunchGraph &) = delete;
+    ~LaunchGraph() { reset(); }
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
 // Last level block ILUT factors (Sec. 3, Alg. 3).
 template <class T>
 struct LastLevel {
@@ -43,6 +59,10 @@ struct LastLevel {
     int waves = 0;                  // kernel launches the factorization took
     double sweep_bytes = 0;         // algorithmic bytes of one forward + backward sweep
     DBuf<double> t;               // solve workspace [n]
+    // the two sweeps captured once as a graph that reads gb and writes gx
+    bool use_graph = true;
+    LaunchGraph sweeps;
+    DBuf<double> gb, gx;          // [n]
 };
 
 template <class T>

@@ -636,13 +636,10 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
     VB_HIP(hipStreamSynchronize(s));
 }
 
+// the level launches of both sweeps: t = L^{-1} b, then x = U^{-1} t (pivot blocks included)
 template <class T>
-void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStream_t s) {
-    (void)err;
-    const int p = last.A.p;
-    if (p == 0) return;
+static void sweep_launches(LastLevel<T> &last, const double *b, double *x, hipStream_t s) {
     const Panel<T> &L = last.L, &U = last.U;
-    KScope ks(VBARMS_K_TRSV, last.sweep_bytes, s);
     for (size_t l = 0; l + 1 < last.lptr.size(); ++l) {
         int cnt = last.lptr[l + 1] - last.lptr[l];
         k_trsv_level<T><<<grid_for(cnt, 4), 256, 0, s>>>(cnt, last.d_lorder.p + last.lptr[l], 0, L.rb.p, L.wp.p,
@@ -657,6 +654,53 @@ void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStr
                                                           last.dl_piv.p, last.t.p, x);
         VB_LAUNCH_CHECK();
     }
+}
+
+// Records the sweeps once on a private stream; the graph reads last.gb and writes last.gx.
+template <class T>
+static void capture_sweeps(LastLevel<T> &last) {
+    const int n = last.A.h_rb.back();
+    last.gb.alloc(std::max(n, 1));
+    last.gx.alloc(std::max(n, 1));
+    hipStream_t cs = nullptr;
+    VB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        try {
+            sweep_launches<T>(last, last.gb.p, last.gx.p, cs);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipStreamDestroy(cs);
+            throw;
+        }
+        e = hipStreamEndCapture(cs, &last.sweeps.graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&last.sweeps.exec, last.sweeps.graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        last.sweeps.reset();
+        fail(VBARMS_ERR_HIP, std::string("capturing the last-level sweeps: ") + hipGetErrorString(e));
+    }
+}
+
+template <class T>
+void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStream_t s) {
+    (void)err;
+    const int p = last.A.p;
+    if (p == 0) return;
+    if (!last.use_graph) {
+        KScope ks(VBARMS_K_TRSV, last.sweep_bytes, s);
+        sweep_launches<T>(last, b, x, s);
+        return;
+    }
+    const int n = last.A.h_rb.back();
+    if (!last.sweeps.exec) capture_sweeps<T>(last);
+    KScope ks(VBARMS_K_TRSV, last.sweep_bytes, s);
+    if (b != last.gb.p) VB_HIP(hipMemcpyAsync(last.gb.p, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    VB_HIP(hipGraphLaunch(last.sweeps.exec, s));
+    if (x != last.gx.p) VB_HIP(hipMemcpyAsync(x, last.gx.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
 }
 
 template void factor_last<double>(LastLevel<double> &, double, int, int *, hipStream_t);

@@ -80,6 +80,7 @@ SIGNATURES = {
     "vbarms_spmv": (C.c_int, [_P, _P, _P]),
     "vbarms_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, C.c_int32, C.POINTER(SInfo)]),
     "vbarms_get_stats": (C.c_int, [_P, C.POINTER(FStats)]),
+    "vbarms_set_graphs": (C.c_int, [_P, C.c_int32]),
     "vbarms_set_timing": (C.c_int, [_P, C.c_int32]),
     "vbarms_kernel_stats": (C.c_int, [_P, C.POINTER(KStat)]),
     "vbarms_num_levels": (C.c_int, [_P, _P]),
@@ -241,6 +242,10 @@ class Solver:
         st = FStats()
         self._check(lib().vbarms_get_stats(self.h, C.byref(st)))
         return st
+
+    def set_graphs(self, enable=True):
+        """Replay the last-level sweeps from a captured graph (default) or launch them eagerly."""
+        self._check(lib().vbarms_set_graphs(self.h, 1 if enable else 0))
 
     def set_timing(self, enable=True):
         """Starts (and clears) or stops event timing of the kernel classes K_*."""

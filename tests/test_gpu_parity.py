@@ -306,3 +306,25 @@ def test_kernel_timing_counts_launches(vb, orc):
         assert ms > 0 and nbytes > 0, name
     sv.set_timing(True)  # clears
     assert all(v[0] == 0 for v in sv.kernel_stats().values())
+
+
+@pytest.mark.parametrize("levels", [0, 2])
+def test_graph_replays_match_eager_launches(vb, orc, levels):
+    import torch
+    s = synth.grid_system(5, 4, 4, ell=4, stencil="14rand", perturb=0.1, seed=88)
+    o, sv, A, st, err = _run_both(vb, orc, s, 0.8, levels, 1e-3)
+    assert err is None
+    rng = np.random.default_rng(3)
+    xs = [torch.as_tensor(rng.standard_normal(s.n), device="cuda") for _ in range(3)]
+    sv.set_graphs(False)
+    eager = [sv.apply(x).cpu() for x in xs]
+    sv.set_graphs(True)
+    # several replays of the captured sweeps, with eager work and synchronizations between
+    for rep in range(3):
+        for x, ye in zip(xs, eager):
+            y = sv.apply(x)
+            sv.spmv(x)
+            torch.cuda.synchronize()
+            assert torch.equal(y.cpu(), ye), f"replay {rep} differs from the eager launches"
+    yo = o.apply(xs[0].cpu().numpy())
+    assert np.abs(eager[0].numpy() - yo).max() <= RTOL * np.abs(yo).max()

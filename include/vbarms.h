@@ -235,6 +235,45 @@ int vbarms_matrix_dims(vbarms_t h, int32_t which, int32_t level, int64_t *dims);
 int vbarms_matrix_get(vbarms_t h, int32_t which, int32_t level, int32_t *rb, int32_t *cb,
                       int64_t *rowptr, int32_t *colidx, double *vals, int32_t *piv);
 
+/* ---------------------------------------------------------------------------------- */
+/* Learned parameter selection.  Not part of the paper's method: a small network that    */
+/* predicts tau and the per-level drop tolerances from features of the matrix.  Callers */
+/* that do not use it run the method with their own parameters.                          */
+/* ---------------------------------------------------------------------------------- */
+#define VBARMS_NFEAT 8
+
+/* Features of A (DEVICE CSR as in vbarms_compress), f (HOST, VBARMS_NFEAT floats):
+ *   0 log10 n                      4 smallest |a_ii| / sum_j |a_ij|
+ *   1 mean row length / 100        5 share of entries below 1e-3 of their row's largest
+ *   2 std / mean of row lengths    6 identical-pattern row classes per row
+ *   3 mean |a_ii| / sum_j |a_ij|   7 mean |a_ij| (j != i) over |a_ii|
+ * Leaves the handle's compressed matrix and factors untouched.  Errors: ARG (n = 0). */
+int vbarms_features(vbarms_t h, const vbarms_csr *A, float *f);
+
+/* Multilayer perceptron: in_dim -> `depth` dense ReLU layers of width `hidden` -> out_dim
+ * (linear), FP32.  Parameters are packed layer by layer as W (n_out x n_in, row-major)
+ * then b (n_out); they start at zero.  Training minimizes the mean squared error
+ * sum (y - t)^2 / (batch * out_dim) with Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * Work runs on `hip_stream`; every call returns after its work has finished. */
+typedef struct vbarms_mlp_ctx *vbarms_mlp_t;
+int vbarms_mlp_create(vbarms_mlp_t *m, int32_t in_dim, int32_t hidden, int32_t depth, int32_t out_dim,
+                      void *hip_stream);
+int vbarms_mlp_destroy(vbarms_mlp_t m);
+const char *vbarms_mlp_last_error(vbarms_mlp_t m);
+int vbarms_mlp_num_params(vbarms_mlp_t m, int64_t *n);
+/* params: DEVICE, num_params floats.  set_params also clears the Adam moments. */
+int vbarms_mlp_set_params(vbarms_mlp_t m, const float *params);
+int vbarms_mlp_get_params(vbarms_mlp_t m, float *params);
+/* x: DEVICE [batch x in_dim] row-major, y: DEVICE [batch x out_dim]. */
+int vbarms_mlp_forward(vbarms_mlp_t m, const float *x, int32_t batch, float *y);
+/* Loss (HOST, may be NULL) and gradient (DEVICE [num_params], may be NULL) for targets
+ * t (DEVICE [batch x out_dim]); the gradient is kept for vbarms_mlp_adam_step. */
+int vbarms_mlp_loss_grad(vbarms_mlp_t m, const float *x, const float *t, int32_t batch, float *loss,
+                         float *grad);
+/* One Adam update with the gradient of the last vbarms_mlp_loss_grad.  Errors: STATE if
+ * there is none, ARG for lr <= 0. */
+int vbarms_mlp_adam_step(vbarms_mlp_t m, float lr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -443,6 +443,15 @@ int vbarms_get_stats(vbarms_t h, vbarms_fstats *st) {
     return VBARMS_OK;
 }
 
+int vbarms_features(vbarms_t h, const vbarms_csr *A, float *f) {
+    return guarded(h, [&] {
+        validate_csr(A);
+        if (!f) fail(VBARMS_ERR_ARG, "NULL feature output");
+        matrix_features(A->n, A->nnz, A->rowptr, A->col, A->val, f, h->stream);
+        return VBARMS_OK;
+    });
+}
+
 int vbarms_set_graphs(vbarms_t h, int32_t enable) {
     return guarded(h, [&] {
         h->graphs = enable != 0;

@@ -123,6 +123,9 @@ struct KrylovWork {
 int fgmres_run(const Panel<double> &A, KrylovWork &kw, const double *b, double *x, double tol, int m, int maxit,
                const std::function<void(const double *, double *)> &precond, vbarms_sinfo *info, hipStream_t s);
 void gather_perm(int n, const int *perm, const double *src, double *dst, hipStream_t s);
+// VBARMS_NFEAT features of a CSR matrix (host output)
+void matrix_features(int n, int64_t nnz, const int64_t *rowptr, const int *col, const double *val, float *f,
+                     hipStream_t s);
 void scatter_perm(int n, const int *perm, const double *src, double *dst, hipStream_t s);
 
 }  // namespace vb

@@ -22,11 +22,23 @@ namespace vb {
 namespace {
 
 constexpr int kIlutThreads = 256;
-constexpr int kHashCap = 2048;  // LDS hash slots: at most kMaxRowBlocks entries
-constexpr int kMaxRowBlocks = 1024;
-constexpr int kMaxM = VBARMS_MAX_BLOCK;
-constexpr int kUStage = 2048;   // values of U row k staged in LDS when they fit
-constexpr int kCheckEvery = 8;  // ILUT waves between host checks
+constexpr int kMaxRowBlocks = 1024;  // largest block list of one working row
+constexpr int kUStage = 1024;        // values of U row k staged in LDS when they fit
+constexpr int kCheckEvery = 8;       // ILUT waves between host checks
+
+// sizes of the dynamic LDS of the ILUT wave kernel
+struct IlutLds {
+    int maxm;    // largest block size
+    int rbcap;   // largest block list of a working row
+    int hcap;    // hash capacity (power of two >= 2 rbcap)
+    int ustage;  // staged values of U row k
+};
+template <class T>
+size_t ilut_lds_bytes(const IlutLds &l) {
+    size_t b = sizeof(T) * ((size_t)2 * l.maxm * l.maxm + l.ustage) + sizeof(int) * ((size_t)2 * l.hcap + 2 * l.rbcap + l.maxm) +
+               (size_t)l.rbcap;
+    return (b + 15) & ~(size_t)15;
+}
 
 struct IlutRowRec {
     int64_t lb, lv, ub, uv;  // block / value offsets in the pools
@@ -36,21 +48,23 @@ struct RowState {
     int nb, used, last_k, status;  // status: 0 not started, 1 started, 2 finished
 };
 
-__device__ inline int h_find(const int *keys, const int *vals, int key) {
-    unsigned h = ((unsigned)key * 2654435761u) & (kHashCap - 1);
+// open-addressing hash in LDS (capacity hmask + 1, a power of two, at least twice the
+// number of keys, so a probe always ends)
+__device__ inline int h_find(const int *keys, const int *vals, unsigned hmask, int key) {
+    unsigned h = ((unsigned)key * 2654435761u) & hmask;
     for (;;) {
         int k = keys[h];
         if (k == key) return vals[h];
         if (k == -1) return -1;
-        h = (h + 1) & (kHashCap - 1);
+        h = (h + 1) & hmask;
     }
 }
-__device__ inline void h_insert(int *keys, int *vals, int key, int val) {
-    unsigned h = ((unsigned)key * 2654435761u) & (kHashCap - 1);
+__device__ inline void h_insert(int *keys, int *vals, unsigned hmask, int key, int val) {
+    unsigned h = ((unsigned)key * 2654435761u) & hmask;
     for (;;) {
         int old = atomicCAS(&keys[h], -1, key);
         if (old == -1 || old == key) { vals[h] = val; return; }
-        h = (h + 1) & (kHashCap - 1);
+        h = (h + 1) & hmask;
     }
 }
 
@@ -71,12 +85,21 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
     double droptol, int *done, RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols, int *woffs,
     unsigned char *west, T *wvals, T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec, int *lci, int *lco,
     T *lv, int *uci, int *uco, T *uv, int64_t *cursors, int64_t capb_pool, int64_t capv_pool, int *err, int lvl,
-    unsigned long long *moved) {
-    __shared__ int hkeys[kHashCap], hvals[kHashCap];
-    __shared__ int l_cols[kMaxRowBlocks], l_offs[kMaxRowBlocks];
-    __shared__ unsigned char l_est[kMaxRowBlocks];  // 0 pending, 1 eliminated, 2 dropped (3/4: kept L/U)
-    __shared__ T s_lu[kMaxM * kMaxM], s_M[kMaxM * kMaxM], s_U[kUStage];
-    __shared__ int s_piv[kMaxM];
+    unsigned long long *moved, IlutLds lds) {
+    // dynamic LDS, carved as described by `lds` (sizes chosen on the host for this matrix)
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *s_lu = (T *)lds_raw;                         // [maxm * maxm] pivot-block LU of row k
+    T *s_M = s_lu + lds.maxm * lds.maxm;            // [maxm * maxm] multiplier block / pivot block
+    T *s_U = s_M + lds.maxm * lds.maxm;             // [ustage] U row k when it fits
+    int *hkeys = (int *)(s_U + lds.ustage);         // [hcap]
+    int *hvals = hkeys + lds.hcap;                  // [hcap]
+    int *l_cols = hvals + lds.hcap;                 // [rbcap] block list of the row
+    int *l_offs = l_cols + lds.rbcap;               // [rbcap]
+    int *s_piv = l_offs + lds.rbcap;                // [maxm]
+    unsigned char *l_est = (unsigned char *)(s_piv + lds.maxm);  // [rbcap] 0 pending, 1 eliminated,
+                                                                 // 2 dropped (3/4: kept L/U)
+    const unsigned hmask = (unsigned)lds.hcap - 1u;
+    const int kRowCap = lds.rbcap;
     __shared__ int s_nb, s_used, s_last, s_status, s_min, s_flag, s_stop, s_ek;
     __shared__ IlutRowRec s_rk;
     __shared__ int s_lc, s_lw, s_uc, s_uw;
@@ -105,7 +128,7 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
         if (r.status == 0) {
             int nA = (int)(rp[i + 1] - rp[i]);
             int64_t W = wp[i + 1] - wp[i];
-            if (nA > CB || nA > kMaxRowBlocks || (int64_t)m * W > CV) {
+            if (nA > CB || nA > kRowCap || m > lds.maxm || (int64_t)m * W > CV) {
                 dev_set_error(err, VBARMS_ERR_OOM, lvl, i);
                 s_stop = 1;
             }
@@ -143,9 +166,9 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
             l_est[e] = est[e];
         }
     }
-    for (int h = t; h < kHashCap; h += kIlutThreads) hkeys[h] = -1;
+    for (int h = t; h < lds.hcap; h += kIlutThreads) hkeys[h] = -1;
     __syncthreads();
-    for (int e = t; e < s_nb; e += kIlutThreads) h_insert(hkeys, hvals, l_cols[e], e);
+    for (int e = t; e < s_nb; e += kIlutThreads) h_insert(hkeys, hvals, hmask, l_cols[e], e);
     __syncthreads();
 
     for (;;) {
@@ -166,7 +189,7 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
                 // the finished row must describe ranges inside the pools
                 const IlutRowRec r = rec[k];
                 const int mk0 = rb[k + 1] - rb[k];
-                int e0 = h_find(hkeys, hvals, k);
+                int e0 = h_find(hkeys, hvals, hmask, k);
                 bool ok = e0 >= 0 && e0 < s_nb && r.uc >= 0 && r.ub >= 0 && r.ub + r.uc <= capb_pool && r.uw >= 0 &&
                           r.uv >= 0 && r.uv + (int64_t)mk0 * r.uw <= capv_pool;
                 if (!ok) {
@@ -199,7 +222,7 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
         const int mk = rb[k + 1] - rb[k];
         const IlutRowRec rk = s_rk;
         const int UW = rk.uw;
-        const bool ustaged = (int64_t)mk * UW <= kUStage;
+        const bool ustaged = (int64_t)mk * UW <= lds.ustage;
         // stage the pivot-block LU of row k, its pivots, the multiplier block and U row k
         {
             const T *dk = dl + dl_off[k];
@@ -245,11 +268,11 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
                 s_stop = 1;
                 continue;
             }
-            if (h_find(hkeys, hvals, J) >= 0) continue;
+            if (h_find(hkeys, hvals, hmask, J) >= 0) continue;
             int nJ = rb[J + 1] - rb[J];
             int e = atomicAdd(&s_nb, 1);
             int off = atomicAdd(&s_used, m * nJ);
-            if (e >= CB || e >= kMaxRowBlocks || (int64_t)off + m * nJ > CV) {
+            if (e >= CB || e >= kRowCap || (int64_t)off + m * nJ > CV) {
                 dev_set_error(err, VBARMS_ERR_OOM, lvl, i);
                 s_stop = 1;
                 continue;
@@ -258,7 +281,7 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
             l_offs[e] = off;
             l_est[e] = 0;
             for (int q = 0; q < m * nJ; ++q) w[off + q] = T(0);
-            h_insert(hkeys, hvals, J, e);
+            h_insert(hkeys, hvals, hmask, J, e);
         }
         __syncthreads();
         if (s_stop) return;
@@ -268,7 +291,7 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
             int J = uci[b];
             int nJ = rb[J + 1] - rb[J];
             int local = c - uco[b];
-            int e = h_find(hkeys, hvals, J);
+            int e = h_find(hkeys, hvals, hmask, J);
             if (e < 0 || local < 0 || local >= nJ) {
                 dev_set_error(err, VBARMS_ERR_HIP, lvl, i);
                 continue;
@@ -287,7 +310,7 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
     }
 
     // finalize row i: pivot block, dropped upper blocks, output to the pools
-    const int ei = h_find(hkeys, hvals, i);
+    const int ei = h_find(hkeys, hvals, hmask, i);
     if (ei >= 0)
         for (int e = t; e < m * m; e += kIlutThreads) s_M[e] = w[l_offs[ei] + e];
     __syncthreads();
@@ -436,59 +459,52 @@ __global__ void k_sq_sizes(int p, const int *rb, int64_t *sq) {
 }
 
 // ---- level-scheduled block substitution ---------------------------------------------
-constexpr int kSolveTG = 8;  // lanes per scalar row
+constexpr int kSweepThreads = 256;
 
 // mode 0: t_i = b_i - sum_k L_ik t_k; mode 1: x_i = D_i^{-1}(t_i - sum_j U_ij x_j).
-// One wavefront per block row of the current level; rows of a level are independent.
-// The pivot-block LU factors and pivots are staged in LDS before the small solve.
-template <class T>
-__global__ void __launch_bounds__(256) k_trsv_level(int nrows, const int *rows, int mode, const int *rb,
-                                                    const int64_t *wp, const int64_t *vp, const int *sc, const T *v,
-                                                    const T *dl, const int64_t *dl_off, const int *dl_piv,
-                                                    const double *b, double *x) {
-    __shared__ double sv[4][VBARMS_MAX_BLOCK];
-    __shared__ T slu[4][VBARMS_MAX_BLOCK * VBARMS_MAX_BLOCK];
-    __shared__ int spiv[4][VBARMS_MAX_BLOCK];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int row = blockIdx.x * 4 + wv;
-    if (row >= nrows) return;
-    const int i = rows[row];
-    const int m = rb[i + 1] - rb[i];
-    const int64_t W = wp[i + 1] - wp[i];
+// One workgroup per block row of the current level (rows of a level are independent).
+// TG lanes share one scalar row of the panel, so each lane handles about W / TG columns;
+// the pivot-block LU factors and pivots are staged in LDS for the small solve.
+template <class T, int TG>
+__global__ void __launch_bounds__(kSweepThreads) k_trsv_level(const int *rows, int mode, const int *rb,
+                                                              const int64_t *wp, const int64_t *vp, const int *sc,
+                                                              const T *v, const T *dl, const int64_t *dl_off,
+                                                              const int *dl_piv, const double *b, double *x) {
+    __shared__ double sv[VBARMS_MAX_BLOCK];
+    __shared__ T slu[VBARMS_MAX_BLOCK * VBARMS_MAX_BLOCK];
+    __shared__ int spiv[VBARMS_MAX_BLOCK];
+    const int t = threadIdx.x;
+    const int i = rows[blockIdx.x];
+    const int r_begin = rb[i];
+    const int m = rb[i + 1] - r_begin;
+    const int64_t w0 = wp[i];
+    const int64_t W = wp[i + 1] - w0;
+    const int64_t v0 = vp[i];
     if (mode == 1) {
         const T *d = dl + dl_off[i];
-        for (int e = lane; e < m * m; e += 64) slu[wv][e] = d[e];
-        if (lane < m) spiv[wv][lane] = dl_piv[rb[i] + lane];
+        for (int e = t; e < m * m; e += kSweepThreads) slu[e] = d[e];
+        if (t < m) spiv[t] = dl_piv[r_begin + t];
     }
-    const int grp = lane / kSolveTG, gl = lane % kSolveTG;
-    for (int r0 = 0; r0 < m; r0 += 64 / kSolveTG) {
+    const int grp = t / TG, gl = t % TG;
+    const int *c = sc + w0;
+    for (int r0 = 0; r0 < m; r0 += kSweepThreads / TG) {
         const int r = r0 + grp;
         double acc = 0.0;
         if (r < m) {
-            const T *a = v + vp[i] + (int64_t)r * W;
-            const int *c = sc + wp[i];
-            for (int64_t j = gl; j < W; j += kSolveTG) acc += (double)a[j] * x[c[j]];
+            const T *a = v + v0 + (int64_t)r * W;
+            for (int64_t j = gl; j < W; j += TG) acc += (double)a[j] * x[c[j]];
         }
 #pragma unroll
-        for (int off = kSolveTG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kSolveTG);
-        if (r < m && gl == 0) sv[wv][r] = b[rb[i] + r] - acc;
+        for (int off = TG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, TG);
+        if (r < m && gl == 0) sv[r] = b[r_begin + r] - acc;
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    if (lane == 0) {
-        double *y = sv[wv];
-        if (mode == 1) {
-            dev_lu_fwd<T, double>(m, slu[wv], spiv[wv], y);
-            dev_lu_bwd<T, double>(m, slu[wv], y);
-        }
+    __syncthreads();
+    if (t == 0 && mode == 1) {
+        dev_lu_fwd<T, double>(m, slu, spiv, sv);
+        dev_lu_bwd<T, double>(m, slu, sv);
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    if (lane < m) x[rb[i] + lane] = sv[wv][lane];
+    __syncthreads();
+    if (t < m) x[r_begin + t] = sv[t];
 }
 
 // level schedule of a triangular block pattern; rows sorted by level, level offsets
@@ -546,6 +562,12 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
     int64_t capb_pool = std::max<int64_t>(4 * A.nb + 1024, 4096);
     int64_t capv_pool = std::max<int64_t>(4 * A.nv + 1024, 65536);
     int grow = 8;
+    int64_t max_na = 0;  // longest block row of the input
+    {
+        std::vector<int64_t> hrp;
+        to_host(hrp, A.rp.p, p + 1, s);
+        for (int i = 0; i < p; ++i) max_na = std::max(max_na, hrp[i + 1] - hrp[i]);
+    }
     for (int attempt = 0; attempt < 4; ++attempt) {
         // per-row working rows
         DBuf<int64_t> capb(p), capv(p), boff(p + 1), voff(p + 1);
@@ -561,6 +583,14 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         DBuf<int> lci(capb_pool), lco(capb_pool), uci(capb_pool), uco(capb_pool);
         DBuf<T> lv(capv_pool), uv(capv_pool);
         DBuf<int64_t> cursors(4);
+        // LDS of the wave kernel: the largest working-row list this attempt allows
+        IlutLds lds;
+        lds.maxm = A.maxm;
+        lds.rbcap = (int)std::min<int64_t>(kMaxRowBlocks, std::max<int64_t>(64, grow * max_na));
+        lds.hcap = 64;
+        while (lds.hcap < 2 * lds.rbcap) lds.hcap *= 2;
+        lds.ustage = kUStage;
+        const size_t lds_bytes = ilut_lds_bytes<T>(lds);
         DBuf<int> done(p), lists(2 * (size_t)p), cnt(3);
         DBuf<unsigned long long> moved(1);
         fill_val<unsigned long long>(moved.p, 0ull, 1, s);
@@ -581,11 +611,11 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
                 const int *in_l = lists.p + (size_t)(launch & 1) * p;
                 int *out_l = lists.p + (size_t)((launch + 1) & 1) * p;
                 KScope ks(VBARMS_K_ILUT, 0.0, s);
-                k_ilut_wave<T><<<known, kIlutThreads, 0, s>>>(
+                k_ilut_wave<T><<<known, kIlutThreads, lds_bytes, s>>>(
                     launch, p, in_l, cnt.p + launch % 3, out_l, cnt.p + (launch + 1) % 3, cnt.p + (launch + 2) % 3,
                     A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p, droptol, done.p, rs.p, boff.p, voff.p,
                     wcols.p, woffs.p, west.p, wvals.p, last.dl.p, last.dl_off.p, last.dl_piv.p, rec.p, lci.p, lco.p,
-                    lv.p, uci.p, uco.p, uv.p, cursors.p, capb_pool, capv_pool, err, lvl, moved.p);
+                    lv.p, uci.p, uco.p, uv.p, cursors.p, capb_pool, capv_pool, err, lvl, moved.p, lds);
                 VB_LAUNCH_CHECK();
             }
             std::vector<int> hc, herr;
@@ -637,23 +667,32 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
 }
 
 // the level launches of both sweeps: t = L^{-1} b, then x = U^{-1} t (pivot blocks included)
-template <class T>
-static void sweep_launches(LastLevel<T> &last, const double *b, double *x, hipStream_t s) {
+template <class T, int TG>
+static void sweep_launches_tg(LastLevel<T> &last, const double *b, double *x, hipStream_t s) {
     const Panel<T> &L = last.L, &U = last.U;
     for (size_t l = 0; l + 1 < last.lptr.size(); ++l) {
         int cnt = last.lptr[l + 1] - last.lptr[l];
-        k_trsv_level<T><<<grid_for(cnt, 4), 256, 0, s>>>(cnt, last.d_lorder.p + last.lptr[l], 0, L.rb.p, L.wp.p,
-                                                          L.vp.p, L.sc.p, L.v.p, last.dl.p, last.dl_off.p,
-                                                          last.dl_piv.p, b, last.t.p);
+        k_trsv_level<T, TG><<<cnt, kSweepThreads, 0, s>>>(last.d_lorder.p + last.lptr[l], 0, L.rb.p, L.wp.p, L.vp.p,
+                                                          L.sc.p, L.v.p, last.dl.p, last.dl_off.p, last.dl_piv.p, b,
+                                                          last.t.p);
         VB_LAUNCH_CHECK();
     }
     for (size_t l = 0; l + 1 < last.uptr.size(); ++l) {
         int cnt = last.uptr[l + 1] - last.uptr[l];
-        k_trsv_level<T><<<grid_for(cnt, 4), 256, 0, s>>>(cnt, last.d_uorder.p + last.uptr[l], 1, U.rb.p, U.wp.p,
-                                                          U.vp.p, U.sc.p, U.v.p, last.dl.p, last.dl_off.p,
-                                                          last.dl_piv.p, last.t.p, x);
+        k_trsv_level<T, TG><<<cnt, kSweepThreads, 0, s>>>(last.d_uorder.p + last.uptr[l], 1, U.rb.p, U.wp.p, U.vp.p,
+                                                          U.sc.p, U.v.p, last.dl.p, last.dl_off.p, last.dl_piv.p,
+                                                          last.t.p, x);
         VB_LAUNCH_CHECK();
     }
+}
+// lanes per scalar row: as many as leave one group per row of the largest block
+template <class T>
+static void sweep_launches(LastLevel<T> &last, const double *b, double *x, hipStream_t s) {
+    const int m = last.A.maxm;
+    if (m <= 4) sweep_launches_tg<T, 64>(last, b, x, s);
+    else if (m <= 8) sweep_launches_tg<T, 32>(last, b, x, s);
+    else if (m <= 16) sweep_launches_tg<T, 16>(last, b, x, s);
+    else sweep_launches_tg<T, 8>(last, b, x, s);
 }
 
 // Records the sweeps once on a private stream; the graph reads last.gb and writes last.gx.

@@ -26,6 +26,7 @@ M_A, M_AS, M_G, M_W, M_D, M_LAST, M_L, M_U, M_DL = range(9)
 K_SPMV, K_APPLY, K_ILUT, K_TRSV, K_ORTHO = range(5)
 K_COUNT = 5
 K_NAMES = ("spmv", "apply", "ilut_wave", "trsv_sweeps", "cgs_pass")
+NFEAT = 8
 
 _ERRNAMES = {ERR_ARG: "ERR_ARG", ERR_HIP: "ERR_HIP", ERR_OOM: "ERR_OOM", ERR_SINGULAR: "ERR_SINGULAR",
              ERR_NAN: "ERR_NAN", ERR_STATE: "ERR_STATE"}
@@ -81,6 +82,16 @@ SIGNATURES = {
     "vbarms_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, C.c_int32, C.POINTER(SInfo)]),
     "vbarms_get_stats": (C.c_int, [_P, C.POINTER(FStats)]),
     "vbarms_set_graphs": (C.c_int, [_P, C.c_int32]),
+    "vbarms_features": (C.c_int, [_P, C.POINTER(_Csr), _P]),
+    "vbarms_mlp_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P]),
+    "vbarms_mlp_destroy": (C.c_int, [_P]),
+    "vbarms_mlp_last_error": (C.c_char_p, [_P]),
+    "vbarms_mlp_num_params": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "vbarms_mlp_set_params": (C.c_int, [_P, _P]),
+    "vbarms_mlp_get_params": (C.c_int, [_P, _P]),
+    "vbarms_mlp_forward": (C.c_int, [_P, _P, C.c_int32, _P]),
+    "vbarms_mlp_loss_grad": (C.c_int, [_P, _P, _P, C.c_int32, C.POINTER(C.c_float), _P]),
+    "vbarms_mlp_adam_step": (C.c_int, [_P, C.c_float]),
     "vbarms_set_timing": (C.c_int, [_P, C.c_int32]),
     "vbarms_kernel_stats": (C.c_int, [_P, C.POINTER(KStat)]),
     "vbarms_num_levels": (C.c_int, [_P, _P]),
@@ -243,6 +254,13 @@ class Solver:
         self._check(lib().vbarms_get_stats(self.h, C.byref(st)))
         return st
 
+    def features(self, rowptr, col, val):
+        """VBARMS_NFEAT features of a device CSR matrix (numpy float32)."""
+        A = self._csr(rowptr, col, val)
+        f = np.zeros(NFEAT, np.float32)
+        self._check(lib().vbarms_features(self.h, C.byref(A), _np_ptr(f)))
+        return f
+
     def set_graphs(self, enable=True):
         """Replay the last-level sweeps from a captured graph (default) or launch them eagerly."""
         self._check(lib().vbarms_set_graphs(self.h, 1 if enable else 0))
@@ -295,6 +313,73 @@ class Solver:
         if piv is not None:
             piv = piv[: rb[-1]]
         return Exported(rb, cb, rowptr, colidx[:nb], vals[:nv], piv)
+
+
+class Mlp:
+    """The parameter-prediction network (FP32, trained by the library's kernels)."""
+
+    def __init__(self, in_dim, hidden, depth, out_dim, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the MLP needs a ROCm GPU")
+        self._torch = torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        rc = lib().vbarms_mlp_create(C.byref(h), in_dim, hidden, depth, out_dim, C.c_void_p(s.cuda_stream))
+        if rc != OK:
+            raise VbarmsError(rc, "vbarms_mlp_create failed")
+        self.h = h
+        self.dims = (in_dim, hidden, depth, out_dim)
+        n = C.c_int64()
+        lib().vbarms_mlp_num_params(self.h, C.byref(n))
+        self.num_params = int(n.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vbarms_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != OK:
+            msg = lib().vbarms_mlp_last_error(self.h)
+            raise VbarmsError(rc, msg.decode() if msg else "")
+
+    def set_params(self, p):
+        t = self._torch.as_tensor(p, dtype=self._torch.float32, device="cuda").contiguous()
+        assert t.numel() == self.num_params
+        self._check(lib().vbarms_mlp_set_params(self.h, _dev_ptr(t, self._torch.float32)))
+
+    def get_params(self):
+        t = self._torch.empty(self.num_params, dtype=self._torch.float32, device="cuda")
+        self._check(lib().vbarms_mlp_get_params(self.h, _dev_ptr(t, self._torch.float32)))
+        return t
+
+    def forward(self, x):
+        torch = self._torch
+        x = torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
+        y = torch.empty((x.shape[0], self.dims[3]), dtype=torch.float32, device="cuda")
+        self._check(lib().vbarms_mlp_forward(self.h, _dev_ptr(x, torch.float32), x.shape[0], _dev_ptr(y, torch.float32)))
+        return y
+
+    def loss_grad(self, x, t, want_grad=True):
+        torch = self._torch
+        x = torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
+        t = torch.as_tensor(t, dtype=torch.float32, device="cuda").contiguous()
+        g = torch.empty(self.num_params, dtype=torch.float32, device="cuda") if want_grad else None
+        loss = C.c_float()
+        self._check(lib().vbarms_mlp_loss_grad(self.h, _dev_ptr(x, torch.float32), _dev_ptr(t, torch.float32),
+                                               x.shape[0], C.byref(loss),
+                                               None if g is None else _dev_ptr(g, torch.float32)))
+        return float(loss.value), g
+
+    def adam_step(self, lr):
+        self._check(lib().vbarms_mlp_adam_step(self.h, C.c_float(lr)))
 
 
 def csr_to_device(system, device="cuda"):

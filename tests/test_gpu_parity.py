@@ -328,3 +328,35 @@ def test_graph_replays_match_eager_launches(vb, orc, levels):
             assert torch.equal(y.cpu(), ye), f"replay {rep} differs from the eager launches"
     yo = o.apply(xs[0].cpu().numpy())
     assert np.abs(eager[0].numpy() - yo).max() <= RTOL * np.abs(yo).max()
+
+
+def test_float32_factors_error_against_fp64_oracle(vb, orc):
+    """X1: with zero dropping the FP32 factors have the oracle's pattern, so every factor
+    is compared value by value; the stated bounds are 1e-4 relative per factor and 1e-5
+    for one application of M^{-1}."""
+    import torch
+    s = synth.grid_system(5, 4, 4, ell=4, stencil="14rand", perturb=0.1, seed=91)
+    o, sv, A, st, err = _run_both(vb, orc, s, 0.8, 2, 0.0, precision=vb.F32)
+    assert err is None and o.status == 0
+    worst = {}
+    for lvl in range(o.nlevels):
+        for w, name in ((vb.M_D, "D"), (vb.M_G, "G"), (vb.M_W, "W")):
+            g, r = sv.matrix(w, lvl), o.matrix(w, lvl)
+            np.testing.assert_array_equal(g.colidx, r.colidx)
+            if r.piv is not None:
+                np.testing.assert_array_equal(g.piv, r.piv)
+            if r.vals.size:
+                worst[f"L{lvl}.{name}"] = np.abs(g.vals - r.vals).max() / np.abs(r.vals).max()
+    for w, name in ((vb.M_L, "L"), (vb.M_U, "U"), (vb.M_DL, "DL")):
+        g, r = sv.matrix(w), o.matrix(w)
+        np.testing.assert_array_equal(g.colidx, r.colidx)
+        if r.vals.size:
+            worst[name] = np.abs(g.vals - r.vals).max() / np.abs(r.vals).max()
+    _say("[case] fp32 factor errors vs fp64 oracle: " + ", ".join(f"{k} {v:.1e}" for k, v in worst.items()))
+    assert max(worst.values()) <= 1e-4
+    x = np.random.default_rng(5).standard_normal(s.n)
+    y = sv.apply(torch.as_tensor(x, device="cuda")).cpu().numpy()
+    yo = o.apply(x)
+    e = np.abs(y - yo).max() / np.abs(yo).max()
+    _say(f"[case] fp32 apply error vs fp64 oracle {e:.1e}")
+    assert e <= 1e-5

@@ -55,7 +55,7 @@ struct LastLevel {
     DBuf<int> dl_piv;             // [n]
     std::vector<int> lorder, lptr;  // forward sweep: block rows sorted by level, level offsets
     std::vector<int> uorder, uptr;  // backward sweep
-    DBuf<int> d_lorder, d_uorder;   // device copies of the two orders
+    DBuf<int64_t> d_lrows, d_urows; // row descriptors of the two sweeps, in sweep order
     int waves = 0;                  // kernel launches the factorization took
     double sweep_bytes = 0;         // algorithmic bytes of one forward + backward sweep
     DBuf<double> t;               // solve workspace [n]

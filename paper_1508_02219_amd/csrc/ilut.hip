@@ -37,7 +37,7 @@ struct IlutLds {
 };
 template <class T>
 size_t ilut_lds_bytes(const IlutLds &l) {
-    size_t b = sizeof(T) * ((size_t)2 * l.maxm * l.maxm + l.ustage) + sizeof(int) * ((size_t)2 * l.hcap + 2 * l.rbcap + l.maxm) +
+    size_t b = sizeof(T) * ((size_t)2 * l.maxm * l.maxm + l.ustage) + sizeof(int) * ((size_t)2 * l.hcap + 6 * l.rbcap + l.maxm) +
                (size_t)l.rbcap;
     return (b + 15) & ~(size_t)15;
 }
@@ -45,6 +45,8 @@ size_t ilut_lds_bytes(const IlutLds &l) {
 struct IlutRowRec {
     int64_t lb, lv, ub, uv;  // block / value offsets in the pools
     int lc, lw, uc, uw;      // block counts and panel widths
+    int64_t lu0;             // offset of the pivot-block LU factors
+    int rbeg, m;             // first scalar row and size of the block row
 };
 struct RowState {
     int nb, used, last_k, status;  // status: 0 not started, 1 started, 2 finished
@@ -97,7 +99,11 @@ __device__ void ilut_row(
     int *hvals = hkeys + lds.hcap;                  // [hcap]
     int *l_cols = hvals + lds.hcap;                 // [rbcap] block list of the row
     int *l_offs = l_cols + lds.rbcap;               // [rbcap]
-    int *s_piv = l_offs + lds.rbcap;                // [maxm]
+    int *s_ucol = l_offs + lds.rbcap;               // [rbcap] U row k: block columns,
+    int *s_uc0 = s_ucol + lds.rbcap;                //   first panel columns,
+    int *s_uoff = s_uc0 + lds.rbcap;                //   offsets of the matching blocks of w,
+    int *s_un = s_uoff + lds.rbcap;                 //   block widths
+    int *s_piv = s_un + lds.rbcap;                  // [maxm]
     unsigned char *l_est = (unsigned char *)(s_piv + lds.maxm);  // [rbcap] 0 pending, 1 eliminated,
                                                                  // 2 dropped (3/4: kept L/U)
     const unsigned hmask = (unsigned)lds.hcap - 1u;
@@ -181,16 +187,18 @@ __device__ void ilut_row(
         const int k = s_min;
         if (k == INT_MAX) break;
         if (t == 0) {
-            // row k is usable only if an earlier launch finished it
+            // row k is usable only if an earlier launch finished it (its record is read
+            // together with the flag and used only then)
             const int dk = done[k];
+            const IlutRowRec r = rec[k];
             s_flag = (dk > 0 && dk < launch) ? 1 : 0;
             if (s_flag) {
                 // the finished row must describe ranges inside the pools
-                const IlutRowRec r = rec[k];
-                const int mk0 = rb[k + 1] - rb[k];
+                const int mk0 = r.m;
                 int e0 = h_find(hkeys, hvals, hmask, k);
-                bool ok = e0 >= 0 && e0 < s_nb && r.uc >= 0 && r.ub >= 0 && r.ub + r.uc <= capb_pool && r.uw >= 0 &&
-                          r.uv >= 0 && r.uv + (int64_t)mk0 * r.uw <= capv_pool;
+                bool ok = e0 >= 0 && e0 < s_nb && r.uc >= 0 && r.uc <= kRowCap && r.ub >= 0 &&
+                          r.ub + r.uc <= capb_pool && r.uw >= 0 && r.uv >= 0 && r.uv + (int64_t)mk0 * r.uw <= capv_pool &&
+                          mk0 >= 1 && mk0 <= lds.maxm && r.rbeg == rb[k] && r.lu0 >= 0;
                 if (!ok) {
                     dev_set_error(err, VBARMS_ERR_HIP, lvl, i);
                     s_flag = 2;
@@ -232,19 +240,24 @@ __device__ void ilut_row(
             return;
         }
         const int ek = s_ek;
-        const int mk = rb[k + 1] - rb[k];
         const IlutRowRec rk = s_rk;
+        const int mk = rk.m;
         const int UW = rk.uw;
         const bool ustaged = (int64_t)mk * UW <= lds.ustage;
         // stage the pivot-block LU of row k, its pivots, the multiplier block and U row k
+        // (values and block lists); all these loads are independent of each other
         {
-            const T *dk = dl + dl_off[k];
+            const T *dk = dl + rk.lu0;
             for (int e = t; e < mk * mk; e += kIlutThreads) s_lu[e] = dk[e];
-            for (int q = t; q < mk; q += kIlutThreads) s_piv[q] = dl_piv[rb[k] + q];
+            for (int q = t; q < mk; q += kIlutThreads) s_piv[q] = dl_piv[rk.rbeg + q];
             const T *Mg = w + l_offs[ek];
             for (int e = t; e < m * mk; e += kIlutThreads) s_M[e] = Mg[e];
             if (ustaged)
                 for (int e = t; e < mk * UW; e += kIlutThreads) s_U[e] = uv[rk.uv + e];
+            for (int b = t; b < rk.uc; b += kIlutThreads) {
+                s_ucol[b] = uci[rk.ub + b];
+                s_uc0[b] = uco[rk.ub + b];
+            }
         }
         __syncthreads();
         if (t < m) {
@@ -273,16 +286,22 @@ __device__ void ilut_row(
             for (int e = t; e < m * mk; e += kIlutThreads) Mg[e] = s_M[e];
         }
         if (t == 0) l_est[ek] = 1;
-        // fill: blocks of U row k not yet in the working row
+        // fill: blocks of U row k not yet in the working row; every block of U row k
+        // records where its counterpart lives in w
         for (int b = t; b < rk.uc; b += kIlutThreads) {
-            int J = uci[rk.ub + b];
-            if (J <= k || J >= p) {
+            const int J = s_ucol[b];
+            const int nJ = (b + 1 < rk.uc ? s_uc0[b + 1] : UW) - s_uc0[b];
+            if (J <= k || J >= p || nJ < 1 || nJ > lds.maxm) {
                 dev_set_error(err, VBARMS_ERR_HIP, lvl, i);
                 s_stop = 1;
                 continue;
             }
-            if (h_find(hkeys, hvals, hmask, J) >= 0) continue;
-            int nJ = rb[J + 1] - rb[J];
+            s_un[b] = nJ;
+            const int e0 = h_find(hkeys, hvals, hmask, J);
+            if (e0 >= 0) {
+                s_uoff[b] = l_offs[e0];
+                continue;
+            }
             int e = atomicAdd(&s_nb, 1);
             int off = atomicAdd(&s_used, m * nJ);
             if (e >= CB || e >= kRowCap || (int64_t)off + m * nJ > CV) {
@@ -293,6 +312,7 @@ __device__ void ilut_row(
             l_cols[e] = J;
             l_offs[e] = off;
             l_est[e] = 0;
+            s_uoff[b] = off;
             for (int q = 0; q < m * nJ; ++q) w[off + q] = T(0);
             h_insert(hkeys, hvals, hmask, J, e);
         }
@@ -300,16 +320,10 @@ __device__ void ilut_row(
         if (s_stop) return;
         // w_J -= M U_kJ for every block J of U row k
         for (int c = t; c < UW; c += kIlutThreads) {
-            int64_t b = dev_floor32(uco, rk.ub, rk.ub + rk.uc, c);
-            int J = uci[b];
-            int nJ = rb[J + 1] - rb[J];
-            int local = c - uco[b];
-            int e = h_find(hkeys, hvals, hmask, J);
-            if (e < 0 || local < 0 || local >= nJ) {
-                dev_set_error(err, VBARMS_ERR_HIP, lvl, i);
-                continue;
-            }
-            T *wj = w + l_offs[e] + local;
+            const int b = (int)dev_floor32(s_uc0, 0, rk.uc, c);
+            const int nJ = s_un[b];
+            const int local = c - s_uc0[b];
+            T *wj = w + s_uoff[b] + local;
             const T *Ug = uv + rk.uv + c;
             for (int r = 0; r < m; ++r) {
                 T acc = wj[r * nJ];
@@ -399,7 +413,7 @@ __device__ void ilut_row(
         }
     }
     if (t == 0) {
-        rec[i] = IlutRowRec{s_lb, s_lv, s_ub, s_uv, s_lc, s_lw, s_uc, s_uw};
+        rec[i] = IlutRowRec{s_lb, s_lv, s_ub, s_uv, s_lc, s_lw, s_uc, s_uw, dl_off[i], rb[i], m};
         rs[i] = RowState{s_nb, s_used, s_last, 2};
         done[i] = launch;
         atomicAdd(nfinished, 1);
@@ -503,50 +517,71 @@ __global__ void k_sq_sizes(int p, const int *rb, int64_t *sq) {
 // ---- level-scheduled block substitution ---------------------------------------------
 constexpr int kSweepThreads = 256;
 
+// Descriptor of one block row of a sweep, stored in level order so that a workgroup needs
+// a single load to find its row.
+struct SweepRow {
+    int i, r_begin, m, pad;
+    int64_t w0, W, v0, lu0;
+};
+
 // mode 0: t_i = b_i - sum_k L_ik t_k; mode 1: x_i = D_i^{-1}(t_i - sum_j U_ij x_j).
 // One workgroup per block row of the current level (rows of a level are independent).
-// TG lanes share one scalar row of the panel, so each lane handles about W / TG columns;
-// the pivot-block LU factors and pivots are staged in LDS for the small solve.
-template <class T, int TG>
-__global__ void __launch_bounds__(kSweepThreads) k_trsv_level(const int *rows, int mode, const int *rb,
-                                                              const int64_t *wp, const int64_t *vp, const int *sc,
-                                                              const T *v, const T *dl, const int64_t *dl_off,
-                                                              const int *dl_piv, const double *b, double *x) {
+// The lanes of the workgroup are split evenly over the m scalar rows of the block row
+// (a power-of-two group per row, at most 64 lanes), each group strides over the panel
+// columns.  In mode 1 the pivot-block LU factors are staged in LDS and the small
+// substitution runs on the first wavefront, one lane per scalar row.
+template <class T>
+__global__ void __launch_bounds__(kSweepThreads) k_trsv_level(const SweepRow *rows, int mode, const int *sc,
+                                                              const T *v, const T *dl, const int *dl_piv,
+                                                              const double *b, double *x) {
     __shared__ double sv[VBARMS_MAX_BLOCK];
     __shared__ T slu[VBARMS_MAX_BLOCK * VBARMS_MAX_BLOCK];
     __shared__ int spiv[VBARMS_MAX_BLOCK];
     const int t = threadIdx.x;
-    const int i = rows[blockIdx.x];
-    const int r_begin = rb[i];
-    const int m = rb[i + 1] - r_begin;
-    const int64_t w0 = wp[i];
-    const int64_t W = wp[i + 1] - w0;
-    const int64_t v0 = vp[i];
+    const SweepRow R = rows[blockIdx.x];
+    const int m = R.m;
     if (mode == 1) {
-        const T *d = dl + dl_off[i];
+        const T *d = dl + R.lu0;
         for (int e = t; e < m * m; e += kSweepThreads) slu[e] = d[e];
-        if (t < m) spiv[t] = dl_piv[r_begin + t];
+        if (t < m) spiv[t] = dl_piv[R.r_begin + t];
     }
-    const int grp = t / TG, gl = t % TG;
-    const int *c = sc + w0;
-    for (int r0 = 0; r0 < m; r0 += kSweepThreads / TG) {
-        const int r = r0 + grp;
-        double acc = 0.0;
-        if (r < m) {
-            const T *a = v + v0 + (int64_t)r * W;
-            for (int64_t j = gl; j < W; j += TG) acc += (double)a[j] * x[c[j]];
+    // lanes per scalar row: the largest power of two with m * tg <= threads, at most 64
+    int tg = 64;
+    while (tg > 1 && m * tg > kSweepThreads) tg >>= 1;
+    const int grp = t / tg, gl = t % tg;
+    const int *c = sc + R.w0;
+    double acc = 0.0;
+    if (grp < m) {
+        const T *a = v + R.v0 + (int64_t)grp * R.W;
+        for (int64_t j = gl; j < R.W; j += tg) acc += (double)a[j] * x[c[j]];
+    }
+    for (int off = tg / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, tg);
+    if (grp < m && gl == 0) sv[grp] = b[R.r_begin + grp] - acc;
+    __syncthreads();
+    if (mode == 1 && t < 64) {
+        // x <- U^{-1} L^{-1} P y with one lane per scalar row (m <= 32)
+        if (t == 0)
+            for (int k = 0; k < m; ++k) {
+                const int pk = spiv[k];
+                if (pk != k) { double tmp = sv[k]; sv[k] = sv[pk]; sv[pk] = tmp; }
+            }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        double y = t < m ? sv[t] : 0.0;
+        for (int k = 0; k + 1 < m; ++k) {
+            const double yk = __shfl(y, k, 64);
+            if (t > k && t < m) y = y - (double)slu[t * m + k] * yk;
         }
-#pragma unroll
-        for (int off = TG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, TG);
-        if (r < m && gl == 0) sv[r] = b[r_begin + r] - acc;
+        for (int k = m - 1; k >= 0; --k) {
+            if (t == k) y = y / (double)slu[k * m + k];
+            const double xk = __shfl(y, k, 64);
+            if (t < k) y = y - (double)slu[t * m + k] * xk;
+        }
+        if (t < m) x[R.r_begin + t] = y;
+    } else if (mode == 0 && t < m) {
+        x[R.r_begin + t] = sv[t];
     }
-    __syncthreads();
-    if (t == 0 && mode == 1) {
-        dev_lu_fwd<T, double>(m, slu, spiv, sv);
-        dev_lu_bwd<T, double>(m, slu, sv);
-    }
-    __syncthreads();
-    if (t < m) x[r_begin + t] = sv[t];
 }
 
 // level schedule of a triangular block pattern; rows sorted by level, level offsets
@@ -705,40 +740,49 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
     // factors and pivots, the row offsets, b, t (written and read) and x
     last.sweep_bytes = (double)sizeof(T) * (double)(last.L.nv + last.U.nv + dtot) + 4.0 * (double)(last.L.nw + last.U.nw) +
                        2.0 * 20.0 * (p + 1) + 4.0 * n + 8.0 * 4.0 * n + 8.0 * p;
-    last.d_lorder.alloc(p);
-    last.d_uorder.alloc(p);
-    to_device(last.d_lorder.p, last.lorder.data(), p, s);
-    to_device(last.d_uorder.p, last.uorder.data(), p, s);
+    // one descriptor per block row, in the order of its sweep
+    {
+        std::vector<int64_t> hdl, lwp, lvp, uwp, uvp;
+        to_host(hdl, last.dl_off.p, p + 1, s);
+        to_host(lwp, last.L.wp.p, p + 1, s);
+        to_host(lvp, last.L.vp.p, p + 1, s);
+        to_host(uwp, last.U.wp.p, p + 1, s);
+        to_host(uvp, last.U.vp.p, p + 1, s);
+        const std::vector<int> &rbh = A.h_rb;
+        std::vector<SweepRow> lr(p), ur(p);
+        for (int q = 0; q < p; ++q) {
+            const int i = last.lorder[q];
+            lr[q] = SweepRow{i, rbh[i], rbh[i + 1] - rbh[i], 0, lwp[i], lwp[i + 1] - lwp[i], lvp[i], hdl[i]};
+            const int j = last.uorder[q];
+            ur[q] = SweepRow{j, rbh[j], rbh[j + 1] - rbh[j], 0, uwp[j], uwp[j + 1] - uwp[j], uvp[j], hdl[j]};
+        }
+        const size_t words = sizeof(SweepRow) / sizeof(int64_t);
+        last.d_lrows.alloc((size_t)p * words);
+        last.d_urows.alloc((size_t)p * words);
+        to_device((SweepRow *)last.d_lrows.p, lr.data(), p, s);
+        to_device((SweepRow *)last.d_urows.p, ur.data(), p, s);
+        VB_HIP(hipStreamSynchronize(s));  // the host vectors are the copy sources
+    }
     VB_HIP(hipStreamSynchronize(s));
 }
 
 // the level launches of both sweeps: t = L^{-1} b, then x = U^{-1} t (pivot blocks included)
-template <class T, int TG>
-static void sweep_launches_tg(LastLevel<T> &last, const double *b, double *x, hipStream_t s) {
+template <class T>
+static void sweep_launches(LastLevel<T> &last, const double *b, double *x, hipStream_t s) {
     const Panel<T> &L = last.L, &U = last.U;
+    const SweepRow *lrows = (const SweepRow *)last.d_lrows.p, *urows = (const SweepRow *)last.d_urows.p;
     for (size_t l = 0; l + 1 < last.lptr.size(); ++l) {
         int cnt = last.lptr[l + 1] - last.lptr[l];
-        k_trsv_level<T, TG><<<cnt, kSweepThreads, 0, s>>>(last.d_lorder.p + last.lptr[l], 0, L.rb.p, L.wp.p, L.vp.p,
-                                                          L.sc.p, L.v.p, last.dl.p, last.dl_off.p, last.dl_piv.p, b,
-                                                          last.t.p);
+        k_trsv_level<T><<<cnt, kSweepThreads, 0, s>>>(lrows + last.lptr[l], 0, L.sc.p, L.v.p, last.dl.p,
+                                                      last.dl_piv.p, b, last.t.p);
         VB_LAUNCH_CHECK();
     }
     for (size_t l = 0; l + 1 < last.uptr.size(); ++l) {
         int cnt = last.uptr[l + 1] - last.uptr[l];
-        k_trsv_level<T, TG><<<cnt, kSweepThreads, 0, s>>>(last.d_uorder.p + last.uptr[l], 1, U.rb.p, U.wp.p, U.vp.p,
-                                                          U.sc.p, U.v.p, last.dl.p, last.dl_off.p, last.dl_piv.p,
-                                                          last.t.p, x);
+        k_trsv_level<T><<<cnt, kSweepThreads, 0, s>>>(urows + last.uptr[l], 1, U.sc.p, U.v.p, last.dl.p,
+                                                      last.dl_piv.p, last.t.p, x);
         VB_LAUNCH_CHECK();
     }
-}
-// lanes per scalar row: as many as leave one group per row of the largest block
-template <class T>
-static void sweep_launches(LastLevel<T> &last, const double *b, double *x, hipStream_t s) {
-    const int m = last.A.maxm;
-    if (m <= 4) sweep_launches_tg<T, 64>(last, b, x, s);
-    else if (m <= 8) sweep_launches_tg<T, 32>(last, b, x, s);
-    else if (m <= 16) sweep_launches_tg<T, 16>(last, b, x, s);
-    else sweep_launches_tg<T, 8>(last, b, x, s);
 }
 
 // Records the sweeps once on a private stream; the graph reads last.gb and writes last.gx.

@@ -23,7 +23,7 @@ namespace {
 
 constexpr int kIlutThreads = 256;
 constexpr int kMaxRowBlocks = 1024;  // largest block list of one working row
-constexpr int kUStage = 1024;        // values of U row k staged in LDS when they fit
+constexpr int kUStage = 1024;        // values of one LDS tile of U row k
 constexpr int kCheckEvery = 8;       // ILUT waves between host checks
 constexpr int kIlutGrid = 1024;      // workgroups of every ILUT launch
 constexpr int kWaitClosed = -2;      // wait-list head of a finished row
@@ -33,7 +33,7 @@ struct IlutLds {
     int maxm;    // largest block size
     int rbcap;   // largest block list of a working row
     int hcap;    // hash capacity (power of two >= 2 rbcap)
-    int ustage;  // staged values of U row k
+    int ustage;  // values of one tile of U row k
 };
 template <class T>
 size_t ilut_lds_bytes(const IlutLds &l) {
@@ -94,7 +94,7 @@ __device__ void ilut_row(
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *s_lu = (T *)lds_raw;                         // [maxm * maxm] pivot-block LU of row k
     T *s_M = s_lu + lds.maxm * lds.maxm;            // [maxm * maxm] multiplier block / pivot block
-    T *s_U = s_M + lds.maxm * lds.maxm;             // [ustage] U row k when it fits
+    T *s_U = s_M + lds.maxm * lds.maxm;             // [ustage] one tile of U row k
     int *hkeys = (int *)(s_U + lds.ustage);         // [hcap]
     int *hvals = hkeys + lds.hcap;                  // [hcap]
     int *l_cols = hvals + lds.hcap;                 // [rbcap] block list of the row
@@ -243,7 +243,6 @@ __device__ void ilut_row(
         const IlutRowRec rk = s_rk;
         const int mk = rk.m;
         const int UW = rk.uw;
-        const bool ustaged = (int64_t)mk * UW <= lds.ustage;
         // stage the pivot-block LU of row k, its pivots, the multiplier block and U row k
         // (values and block lists); all these loads are independent of each other
         {
@@ -252,8 +251,6 @@ __device__ void ilut_row(
             for (int q = t; q < mk; q += kIlutThreads) s_piv[q] = dl_piv[rk.rbeg + q];
             const T *Mg = w + l_offs[ek];
             for (int e = t; e < m * mk; e += kIlutThreads) s_M[e] = Mg[e];
-            if (ustaged)
-                for (int e = t; e < mk * UW; e += kIlutThreads) s_U[e] = uv[rk.uv + e];
             for (int b = t; b < rk.uc; b += kIlutThreads) {
                 s_ucol[b] = uci[rk.ub + b];
                 s_uc0[b] = uco[rk.ub + b];
@@ -318,20 +315,27 @@ __device__ void ilut_row(
         }
         __syncthreads();
         if (s_stop) return;
-        // w_J -= M U_kJ for every block J of U row k
-        for (int c = t; c < UW; c += kIlutThreads) {
-            const int b = (int)dev_floor32(s_uc0, 0, rk.uc, c);
-            const int nJ = s_un[b];
-            const int local = c - s_uc0[b];
-            T *wj = w + s_uoff[b] + local;
-            const T *Ug = uv + rk.uv + c;
-            for (int r = 0; r < m; ++r) {
-                T acc = wj[r * nJ];
-                for (int q = 0; q < mk; ++q) acc = acc - s_M[r * mk + q] * (ustaged ? s_U[q * UW + c] : Ug[(int64_t)q * UW]);
-                wj[r * nJ] = acc;
+        // w_J -= M U_kJ for every block J of U row k; U row k is staged in LDS one tile of
+        // columns at a time and the threads share the (row, column) pairs of the tile
+        const int TW = lds.ustage / mk;
+        for (int c0 = 0; c0 < UW; c0 += TW) {
+            const int tw = UW - c0 < TW ? UW - c0 : TW;
+            for (int e = t; e < mk * tw; e += kIlutThreads) {
+                const int q = e / tw, cc = e - q * tw;
+                s_U[q * tw + cc] = uv[rk.uv + (int64_t)q * UW + c0 + cc];
             }
+            __syncthreads();
+            for (int e = t; e < m * tw; e += kIlutThreads) {
+                const int r = e / tw, cc = e - r * tw, c = c0 + cc;
+                const int b = (int)dev_floor32(s_uc0, 0, rk.uc, c);
+                const int nJ = s_un[b];
+                T *wj = w + s_uoff[b] + (c - s_uc0[b]) + r * nJ;
+                T acc = *wj;
+                for (int q = 0; q < mk; ++q) acc = acc - s_M[r * mk + q] * s_U[q * tw + cc];
+                *wj = acc;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         if (t == 0) s_last = k;
         __syncthreads();
     }
@@ -636,8 +640,6 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         last.U.rp.alloc(1); fill_i64(last.U.rp.p, 0, 1, s); panel_finish_layout(last.U, s);
         return;
     }
-    int64_t capb_pool = std::max<int64_t>(4 * A.nb + 1024, 4096);
-    int64_t capv_pool = std::max<int64_t>(4 * A.nv + 1024, 65536);
     int grow = 8;
     int64_t max_na = 0;  // longest block row of the input
     {
@@ -657,6 +659,9 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         DBuf<T> wvals(totv);
         DBuf<RowState> rs(p);
         DBuf<IlutRowRec> rec(p);
+        // a row's L and U output never exceed its working row, so pools as large as all
+        // working rows together cannot overflow
+        const int64_t capb_pool = std::max<int64_t>(totb, 1), capv_pool = std::max<int64_t>(totv, 1);
         DBuf<int> lci(capb_pool), lco(capb_pool), uci(capb_pool), uco(capb_pool);
         DBuf<T> lv(capv_pool), uv(capv_pool);
         DBuf<int64_t> cursors(4);
@@ -716,9 +721,9 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
             if (kt && kt->on) kt->tot[VBARMS_K_ILUT].bytes += (double)read_one(moved.p, s);
         }
         if (code == VBARMS_ERR_OOM && attempt < 3) {
-            // a working row or a pool outgrew its capacity: start again with more room
-            if (eblock == -1) { capb_pool *= 3; capv_pool *= 3; }
-            else grow *= 3;
+            // a working row outgrew its capacity: start again with more room
+            (void)eblock;
+            grow *= 3;
             continue;
         }
         if (code != 0) return;  // reported by the caller from the error record

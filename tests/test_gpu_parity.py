@@ -360,3 +360,13 @@ def test_float32_factors_error_against_fp64_oracle(vb, orc):
     e = np.abs(y - yo).max() / np.abs(yo).max()
     _say(f"[case] fp32 apply error vs fp64 oracle {e:.1e}")
     assert e <= 1e-5
+
+
+@pytest.mark.parametrize("levels", [0, 1])
+def test_wide_upper_rows_span_several_lds_tiles(vb, orc, levels):
+    # 8 unknowns per node and no dropping: last-level U rows are wider than one LDS tile
+    # of the elimination update, which then runs tile by tile
+    s = synth.grid_system(4, 3, 3, ell=8, stencil="14rand", seed=5)
+    o, sv, A, st, err = _run_both(vb, orc, s, 1.0, levels, 0.0)
+    assert err is None and o.status == 0
+    _check_all_factors(vb, orc, o, sv)

@@ -26,7 +26,7 @@ constexpr int kMaxRowBlocks = 1024;  // largest block list of one working row
 constexpr int kUStage = 1024;        // values of one LDS tile of U row k
 constexpr int kCheckEvery = 8;       // ILUT waves between host checks
 constexpr int kIlutGrid = 1024;      // workgroups of every ILUT launch
-constexpr int kWaitClosed = -2;      // wait-list head of a finished row
+constexpr int kGatherBlocks = 256;   // workgroups of the gather kernel
 
 // sizes of the dynamic LDS of the ILUT wave kernel
 struct IlutLds {
@@ -80,11 +80,11 @@ __device__ inline void h_insert(int *keys, int *vals, unsigned hmask, int key, i
 // small dense solves, which keep the operation order of the sequential algorithm.  A row
 // that meets an unfinished row k saves its list and appends itself to the output list.
 //
-// Counters rotate over three slots: launch L reads cnt_in, appends to cnt_out and clears
-// cnt_clear, which launch L-1 read and launch L+1 will append to.
+// A row that meets an unfinished row k records k and appends itself to the waiting list;
+// the gather kernel of a later launch returns it to the ready list once k has finished.
 template <class T>
 __device__ void ilut_row(
-    const int i, int launch, int p, int *act_out, int *cnt_out, int *wait_head, int *wait_next, int *nfinished,
+    const int i, int launch, int p, int *wait_out, int *cnt_wait_out, int *wait_on, int *nfinished,
     const int *rb, const int64_t *rp, const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av,
     double droptol, int *done, RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols, int *woffs,
     unsigned char *west, T *wvals, T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec, int *lci, int *lco,
@@ -219,21 +219,9 @@ __device__ void ilut_row(
                 if (t == 0) {
                     rs[i] = RowState{s_nb, s_used, s_last, 1};
                     nbytes += 9ull * s_nb + 24;
-                    // wait on row k: push onto its list; if k has already closed its list
-                    // (it finished during this launch) queue the row for the next launch
-                    __threadfence();  // the saved state is visible before the row can be woken
-                    int head = __hip_atomic_load(&wait_head[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    for (;;) {
-                        if (head == kWaitClosed) {
-                            act_out[atomicAdd(cnt_out, 1)] = i;
-                            break;
-                        }
-                        wait_next[i] = head;
-                        __threadfence();  // the link is visible before the push
-                        const int prev = atomicCAS(&wait_head[k], head, i);
-                        if (prev == head) break;
-                        head = prev;
-                    }
+                    // wait on row k; everything written here is read in a later launch
+                    wait_on[i] = k;
+                    wait_out[atomicAdd(cnt_wait_out, 1)] = i;
                 }
             }
             if (t == 0) atomicAdd(moved, nbytes);
@@ -421,36 +409,48 @@ __device__ void ilut_row(
         rs[i] = RowState{s_nb, s_used, s_last, 2};
         done[i] = launch;
         atomicAdd(nfinished, 1);
-        // close the wait list and queue every row waiting on this one for the next launch
-        __threadfence();
-        int w = atomicExch(&wait_head[i], kWaitClosed);
-        __threadfence();
-        for (int guard = 0; w >= 0 && guard < p; ++guard) {
-            const int nx = wait_next[w];
-            act_out[atomicAdd(cnt_out, 1)] = w;
-            w = nx;
-        }
         // pivot block in and its LU out, kept blocks copied to the pools, the records
         nbytes += 2ull * S * m * m + 4ull * m + 2ull * S * m * (s_lw + s_uw) + 8ull * (s_lc + s_uc) + 72;
         atomicAdd(moved, nbytes);
     }
 }
 
-// One launch: a fixed grid strides over the rows of the input list.
+// Gather of a launch: waiting rows whose awaited row has finished (in an earlier launch)
+// move to the ready list, the others stay on the waiting list.  Rows that never ran wait
+// on nothing (-1).
+__global__ void k_ilut_gather(const int *wait_in, const int *cnt_wait_in, const int *wait_on, const int *done,
+                              int *ready, int *cnt_ready, int *wait_out, int *cnt_wait_out) {
+    const int n = *cnt_wait_in;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int i = wait_in[e];
+        const int k = wait_on[i];
+        if (k < 0 || done[k] != 0) ready[atomicAdd(cnt_ready, 1)] = i;
+        else wait_out[atomicAdd(cnt_wait_out, 1)] = i;
+    }
+}
+
+// One launch: a fixed grid strides over the ready list.  Counter slots: the gather of
+// launch L fills the ready count and the waiting count this launch appends to; the wave
+// clears the ready count of launch L+1 and the waiting count launch L+1 will append to,
+// both last read by launch L-1.
 template <class T>
 __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
-    int launch, int p, const int *act_in, const int *cnt_in, int *act_out, int *cnt_out, int *cnt_clear,
-    int *wait_head, int *wait_next, int *nfinished, const int *rb, const int64_t *rp, const int *ci, const int *co,
-    const int64_t *wp, const int64_t *vp, const T *av, double droptol, int *done, RowState *rs, const int64_t *boff,
-    const int64_t *voff, int *wcols, int *woffs, unsigned char *west, T *wvals, T *dl, const int64_t *dl_off,
-    int *dl_piv, IlutRowRec *rec, int *lci, int *lco, T *lv, int *uci, int *uco, T *uv, int64_t *cursors,
-    int64_t capb_pool, int64_t capv_pool, int *err, int lvl, unsigned long long *moved, IlutLds lds) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_clear = 0;
-    const int nin = *cnt_in;
+    int launch, int p, const int *ready, const int *cnt_ready, int *cnt_ready_clear, int *wait_out,
+    int *cnt_wait_out, int *cnt_wait_clear, int *wait_on, int *nfinished, const int *rb, const int64_t *rp,
+    const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av, double droptol, int *done,
+    RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols, int *woffs, unsigned char *west, T *wvals,
+    T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec, int *lci, int *lco, T *lv, int *uci, int *uco, T *uv,
+    int64_t *cursors, int64_t capb_pool, int64_t capv_pool, int *err, int lvl, unsigned long long *moved,
+    IlutLds lds) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *cnt_ready_clear = 0;
+        *cnt_wait_clear = 0;
+    }
+    const int nin = *cnt_ready;
     for (int slot = blockIdx.x; slot < nin; slot += gridDim.x) {
-        ilut_row<T>(act_in[slot], launch, p, act_out, cnt_out, wait_head, wait_next, nfinished, rb, rp, ci, co, wp,
-                    vp, av, droptol, done, rs, boff, voff, wcols, woffs, west, wvals, dl, dl_off, dl_piv, rec, lci, lco,
-                    lv, uci, uco, uv, cursors, capb_pool, capv_pool, err, lvl, moved, lds);
+        ilut_row<T>(ready[slot], launch, p, wait_out, cnt_wait_out, wait_on, nfinished, rb, rp, ci, co, wp, vp, av,
+                    droptol, done, rs, boff, voff, wcols, woffs, west, wvals, dl, dl_off, dl_piv, rec, lci, lco, lv, uci,
+                    uco, uv, cursors, capb_pool, capv_pool, err, lvl, moved, lds);
         __syncthreads();
     }
 }
@@ -673,44 +673,48 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         while (lds.hcap < 2 * lds.rbcap) lds.hcap *= 2;
         lds.ustage = kUStage;
         const size_t lds_bytes = ilut_lds_bytes<T>(lds);
-        // cnt: three rotating list counters, then the number of finished rows
-        DBuf<int> done(p), lists(2 * (size_t)p), cnt(4), wait_head(p), wait_next(p);
+        // cnt: three rotating waiting-list counters, two ready counters, finished rows
+        DBuf<int> done(p), waits(2 * (size_t)p), ready(p), wait_on(p), cnt(6);
         DBuf<unsigned long long> moved(1);
         fill_val<unsigned long long>(moved.p, 0ull, 1, s);
         VB_HIP(hipMemsetAsync(rs.p, 0, sizeof(RowState) * p, s));
         fill_i64(cursors.p, 0, 4, s);
         fill_i32(done.p, 0, p, s);
-        fill_i32(wait_head.p, -1, p, s);
-        iota_i32(lists.p + p, p, s);  // list of launch 1 (odd launches read the second list)
-        const int cnt0[4] = {0, p, 0, 0};
-        to_device(cnt.p, cnt0, 4, s);
+        fill_i32(wait_on.p, -1, p, s);
+        iota_i32(waits.p + p, p, s);  // waiting list of launch 1 (odd launches read the second list)
+        const int cnt0[6] = {0, p, 0, 0, 0, 0};
+        to_device(cnt.p, cnt0, 6, s);
         VB_HIP(hipMemsetAsync(err, 0, 4 * sizeof(int), s));
+        int *cw = cnt.p, *cr = cnt.p + 3, *nfin = cnt.p + 5;
         const unsigned grid = (unsigned)std::min(p, kIlutGrid);
         int finished = 0, launch = 0, code = 0, eblock = 0;
         while (finished < p) {
             // every launch finishes at least one row: the smallest unfinished row depends only
-            // on rows finished in earlier launches, and is always in the launch's list
+            // on rows finished in earlier launches, so the gather always finds it ready
             if (launch > p + kCheckEvery) fail(VBARMS_ERR_HIP, "block ILUT made no progress");
             for (int q = 0; q < kCheckEvery; ++q) {
                 ++launch;
-                const int *in_l = lists.p + (size_t)(launch & 1) * p;
-                int *out_l = lists.p + (size_t)((launch + 1) & 1) * p;
+                const int *w_in = waits.p + (size_t)(launch & 1) * p;
+                int *w_out = waits.p + (size_t)((launch + 1) & 1) * p;
+                k_ilut_gather<<<kGatherBlocks, 256, 0, s>>>(w_in, cw + launch % 3, wait_on.p, done.p, ready.p,
+                                                            cr + launch % 2, w_out, cw + (launch + 1) % 3);
+                VB_LAUNCH_CHECK();
                 KScope ks(VBARMS_K_ILUT, 0.0, s);
                 k_ilut_wave<T><<<grid, kIlutThreads, lds_bytes, s>>>(
-                    launch, p, in_l, cnt.p + launch % 3, out_l, cnt.p + (launch + 1) % 3, cnt.p + (launch + 2) % 3,
-                    wait_head.p, wait_next.p, cnt.p + 3, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p,
+                    launch, p, ready.p, cr + launch % 2, cr + (launch + 1) % 2, w_out, cw + (launch + 1) % 3,
+                    cw + (launch + 2) % 3, wait_on.p, nfin, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p,
                     droptol, done.p, rs.p, boff.p, voff.p, wcols.p, woffs.p, west.p, wvals.p, last.dl.p,
                     last.dl_off.p, last.dl_piv.p, rec.p, lci.p, lco.p, lv.p, uci.p, uco.p, uv.p, cursors.p, capb_pool,
                     capv_pool, err, lvl, moved.p, lds);
                 VB_LAUNCH_CHECK();
             }
             std::vector<int> hc, herr;
-            to_host(hc, cnt.p, 4, s);
+            to_host(hc, cnt.p, 6, s);
             to_host(herr, err, 4, s);
             code = herr[0];
             eblock = herr[2];
             if (code != 0) break;
-            const int now = hc[3];
+            const int now = hc[5];
             if (now < p && now < finished + kCheckEvery) fail(VBARMS_ERR_HIP, "block ILUT made no progress");
             finished = now;
         }

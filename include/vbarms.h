@@ -108,6 +108,8 @@ typedef struct {
     int32_t last_p;          /* supernodes handed to the last-level ILUT */
     int64_t factor_values;   /* stored values of all factors (Mem = factor_values / nnz(A)) */
     int64_t nnz;             /* nnz(A) */
+    int32_t spmv_lanes;      /* lanes per scalar row of the FGMRES product, picked at compression by
+                                timing 4, 8, 16 and 32 on the compressed matrix */
 } vbarms_fstats;
 
 /* Creates a handle bound to the current HIP device and to `hip_stream` (a hipStream_t,

@@ -116,6 +116,7 @@ void finish_partition(vbarms_t h, const vbarms_csr *A, vbarms_cstats *st) {
     h->A = Panel<double>();
     panel_from_csr(A->n, A->rowptr, A->col, A->val, h->perm.p, h->bptr, h->A, h->err.rec.p, s);
     check_dev_err(h, "compress");
+    h->stats.spmv_lanes = autotune_spmv<double>(h->A, s);
     h->have_A = true;
     h->have_factors = false;
     h->f64.reset();

@@ -213,6 +213,7 @@ struct Panel {
     DBuf<int> sc;              // [nw]
     DBuf<int> rowblk;          // [n] block row of every scalar row
     DBuf<T> v;                 // [nv]
+    int tg = 8;                // lanes per scalar row of the product kernel (autotuned)
 };
 
 // Raw view passed to kernels
@@ -389,5 +390,7 @@ template <class T>
 void panel_spmv(const Panel<T> &a, const double *x, double *y, hipStream_t s);
 template <class T>
 double panel_spmv_bytes(const Panel<T> &a, bool with_b);
+template <class T>
+int autotune_spmv(Panel<T> &a, hipStream_t s);
 
 }  // namespace vb

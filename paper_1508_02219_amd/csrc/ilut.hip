@@ -179,9 +179,18 @@ __device__ void ilut_row(
     for (;;) {
         if (t == 0) s_min = INT_MAX;
         __syncthreads();
-        for (int e = t; e < s_nb; e += kIlutThreads) {
-            int K = l_cols[e];
-            if (K < i && K > s_last && l_est[e] == 0) atomicMin(&s_min, K);
+        {
+            int mine = INT_MAX;
+            for (int e = t; e < s_nb; e += kIlutThreads) {
+                const int K = l_cols[e];
+                if (K < i && K > s_last && l_est[e] == 0 && K < mine) mine = K;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const int o = __shfl_xor(mine, off, 64);
+                mine = o < mine ? o : mine;
+            }
+            if ((t & 63) == 0 && mine != INT_MAX) atomicMin(&s_min, mine);
         }
         __syncthreads();
         const int k = s_min;
@@ -418,14 +427,41 @@ __device__ void ilut_row(
 // Gather of a launch: waiting rows whose awaited row has finished (in an earlier launch)
 // move to the ready list, the others stay on the waiting list.  Rows that never ran wait
 // on nothing (-1).
-__global__ void k_ilut_gather(const int *wait_in, const int *cnt_wait_in, const int *wait_on, const int *done,
-                              int *ready, int *cnt_ready, int *wait_out, int *cnt_wait_out) {
+// Appends are aggregated per wavefront (one atomic per list and wavefront).
+__device__ inline int wave_append(bool take, int *counter) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long mask = __ballot(take);
+    const int total = __popcll(mask);
+    int base = 0;
+    if (total > 0) {
+        const int leader = __ffsll((long long)mask) - 1;
+        if (lane == leader) base = atomicAdd(counter, total);
+        base = __shfl(base, leader, 64);
+    }
+    return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+__global__ void __launch_bounds__(256) k_ilut_gather(const int *wait_in, const int *cnt_wait_in, const int *wait_on,
+                                                     const int *done, int *ready, int *cnt_ready, int *wait_out,
+                                                     int *cnt_wait_out) {
     const int n = *cnt_wait_in;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const int i = wait_in[e];
-        const int k = wait_on[i];
-        if (k < 0 || done[k] != 0) ready[atomicAdd(cnt_ready, 1)] = i;
-        else wait_out[atomicAdd(cnt_wait_out, 1)] = i;
+    const int stride = gridDim.x * blockDim.x;
+    // every lane of a wavefront takes part in each round, so the ballots see all of them
+    for (int e0 = blockIdx.x * blockDim.x; e0 < n; e0 += stride) {
+        const int e = e0 + (int)threadIdx.x;
+        int i = -1;
+        bool rdy = false;
+        if (e < n) {
+            i = wait_in[e];
+            const int k = wait_on[i];
+            rdy = k < 0 || done[k] != 0;
+        }
+        const int pr = wave_append(e < n && rdy, cnt_ready);
+        const int pw = wave_append(e < n && !rdy, cnt_wait_out);
+        if (e < n) {
+            if (rdy) ready[pr] = i;
+            else wait_out[pw] = i;
+        }
     }
 }
 

@@ -35,13 +35,61 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n, const int *__restrict__
 
 }  // namespace
 
+// Lanes per scalar row: as many lanes as the autotuner picked for this matrix.
 template <class T>
 void panel_spmv_ex(const Panel<T> &a, const double *x, const double *b, double *y, hipStream_t s) {
     int64_t n = a.h_rb.empty() ? 0 : a.h_rb.back();
     if (n == 0) return;
-    constexpr int TG = 8;
-    k_spmv<T, TG><<<grid_for(n * TG, 256), 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p, x, b, y);
+    switch (a.tg) {
+    case 4:
+        k_spmv<T, 4><<<grid_for(n * 4, 256), 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p, x, b, y);
+        break;
+    case 16:
+        k_spmv<T, 16><<<grid_for(n * 16, 256), 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p, x, b, y);
+        break;
+    case 32:
+        k_spmv<T, 32><<<grid_for(n * 32, 256), 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p, x, b, y);
+        break;
+    default:
+        k_spmv<T, 8><<<grid_for(n * 8, 256), 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p, x, b, y);
+        break;
+    }
     VB_LAUNCH_CHECK();
+}
+
+// Times the product with 4, 8, 16 and 32 lanes per scalar row on this matrix (one warm-up
+// and five timed runs each, HIP events on the stream) and keeps the fastest.
+template <class T>
+int autotune_spmv(Panel<T> &a, hipStream_t s) {
+    const int64_t n = a.h_rb.empty() ? 0 : a.h_rb.back();
+    const int64_t ncol = a.h_cb.empty() ? 0 : a.h_cb.back();
+    a.tg = 8;
+    if (n == 0 || ncol == 0) return a.tg;
+    DBuf<double> x(ncol), y(n);
+    fill_val<double>(x.p, 1.0, ncol, s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    VB_HIP(hipEventCreate(&e0));
+    VB_HIP(hipEventCreate(&e1));
+    float best = 0.f;
+    int best_tg = 8;
+    for (int tg : {4, 8, 16, 32}) {
+        a.tg = tg;
+        panel_spmv_ex<T>(a, x.p, nullptr, y.p, s);
+        VB_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 5; ++r) panel_spmv_ex<T>(a, x.p, nullptr, y.p, s);
+        VB_HIP(hipEventRecord(e1, s));
+        VB_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        VB_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (tg == 4 || ms < best) {
+            best = ms;
+            best_tg = tg;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    a.tg = best_tg;
+    return best_tg;
 }
 
 // Bytes one product must move: the values, one column index per panel column, the
@@ -65,5 +113,7 @@ template void panel_spmv<double>(const Panel<double> &, const double *, double *
 template void panel_spmv<float>(const Panel<float> &, const double *, double *, hipStream_t);
 template void panel_spmv_ex<double>(const Panel<double> &, const double *, const double *, double *, hipStream_t);
 template void panel_spmv_ex<float>(const Panel<float> &, const double *, const double *, double *, hipStream_t);
+template int autotune_spmv<double>(Panel<double> &, hipStream_t);
+template int autotune_spmv<float>(Panel<float> &, hipStream_t);
 
 }  // namespace vb

@@ -60,7 +60,8 @@ class SInfo(C.Structure):
 class FStats(C.Structure):
     _fields_ = [("compress_ms", C.c_double), ("factor_ms", C.c_double), ("solve_ms", C.c_double),
                 ("factor_level_ms", C.c_double * MAX_LEVELS), ("ilut_ms", C.c_double), ("levels", C.c_int32),
-                ("last_p", C.c_int32), ("factor_values", C.c_int64), ("nnz", C.c_int64)]
+                ("last_p", C.c_int32), ("factor_values", C.c_int64), ("nnz", C.c_int64),
+                ("spmv_lanes", C.c_int32)]
 
 
 class KStat(C.Structure):

@@ -370,3 +370,19 @@ def test_wide_upper_rows_span_several_lds_tiles(vb, orc, levels):
     o, sv, A, st, err = _run_both(vb, orc, s, 1.0, levels, 0.0)
     assert err is None and o.status == 0
     _check_all_factors(vb, orc, o, sv)
+
+
+def test_spmv_lanes_autotuned_and_product_exact(vb):
+    import torch
+    import scipy.sparse as sp
+    for s in (synth.grid_system(6, 5, 4, ell=5, stencil="14rand", perturb=0.1, seed=12),
+              synth.random_pattern_matrix(500, 0.01, twins=100, seed=13, diag=5.0)):
+        sv = vb.Solver()
+        sv.compress(*vb.csr_to_device(s), 0.8)
+        lanes = sv.stats().spmv_lanes
+        _say(f"[case] {s.name}: autotuned lanes per row {lanes}")
+        assert lanes in (4, 8, 16, 32)
+        x = np.random.default_rng(2).standard_normal(s.n)
+        ax = sv.spmv(torch.as_tensor(x, device="cuda")).cpu().numpy()
+        a = sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n))
+        assert np.abs(ax - a @ x).max() <= 1e-13 * np.abs(a @ x).max()

@@ -32,7 +32,7 @@ constexpr int kGatherBlocks = 256;   // workgroups of the gather kernel
 struct IlutLds {
     int maxm;    // largest block size
     int rbcap;   // largest block list of a working row
-    int hcap;    // hash capacity (power of two >= 2 rbcap)
+    int hcap;    // hash capacity (power of two >= 1.5 rbcap)
     int ustage;  // values of one tile of U row k
 };
 template <class T>
@@ -52,8 +52,8 @@ struct RowState {
     int nb, used, last_k, status;  // status: 0 not started, 1 started, 2 finished
 };
 
-// open-addressing hash in LDS (capacity hmask + 1, a power of two, at least twice the
-// number of keys, so a probe always ends)
+// open-addressing hash in LDS (capacity hmask + 1, a power of two, at least 1.5 times the
+// number of keys, so a probe always ends at a free slot)
 __device__ inline int h_find(const int *keys, const int *vals, unsigned hmask, int key) {
     unsigned h = ((unsigned)key * 2654435761u) & hmask;
     for (;;) {
@@ -108,7 +108,7 @@ __device__ void ilut_row(
                                                                  // 2 dropped (3/4: kept L/U)
     const unsigned hmask = (unsigned)lds.hcap - 1u;
     const int kRowCap = lds.rbcap;
-    __shared__ int s_nb, s_used, s_last, s_status, s_min, s_flag, s_stop, s_ek;
+    __shared__ int s_nb, s_used, s_last, s_status, s_min, s_flag, s_stop, s_ek, s_nb0;
     __shared__ IlutRowRec s_rk;
     __shared__ int s_lc, s_lw, s_uc, s_uw;
     __shared__ int64_t s_lb, s_lv, s_ub, s_uv;
@@ -172,6 +172,8 @@ __device__ void ilut_row(
         }
     }
     for (int h = t; h < lds.hcap; h += kIlutThreads) hkeys[h] = -1;
+    // entries below s_nb0 are already in the row's global list (not on a first visit)
+    if (t == 0) s_nb0 = s_status == 0 ? 0 : s_nb;
     __syncthreads();
     for (int e = t; e < s_nb; e += kIlutThreads) h_insert(hkeys, hvals, hmask, l_cols[e], e);
     __syncthreads();
@@ -219,10 +221,13 @@ __device__ void ilut_row(
         __syncthreads();
         if (s_flag != 1) {
             if (s_flag == 0) {
-                // not finished yet: save the list and state, queue the row for the next launch
+                // not finished yet: save the state of the list (the columns and offsets of
+                // entries loaded at the start of this visit are unchanged)
                 for (int e = t; e < s_nb; e += kIlutThreads) {
-                    cols[e] = l_cols[e];
-                    offs[e] = l_offs[e];
+                    if (e >= s_nb0) {
+                        cols[e] = l_cols[e];
+                        offs[e] = l_offs[e];
+                    }
                     est[e] = l_est[e];
                 }
                 if (t == 0) {
@@ -705,8 +710,9 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         IlutLds lds;
         lds.maxm = A.maxm;
         lds.rbcap = (int)std::min<int64_t>(kMaxRowBlocks, std::max<int64_t>(64, grow * max_na));
+        // hash load stays below two thirds, and a free slot always ends a probe
         lds.hcap = 64;
-        while (lds.hcap < 2 * lds.rbcap) lds.hcap *= 2;
+        while (2 * lds.hcap < 3 * lds.rbcap) lds.hcap *= 2;
         lds.ustage = kUStage;
         const size_t lds_bytes = ilut_lds_bytes<T>(lds);
         // cnt: three rotating waiting-list counters, two ready counters, finished rows

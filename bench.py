@@ -157,6 +157,9 @@ def main() -> int:
         "levels_factored": fs.levels,
         "last_level_supernodes": fs.last_p,
         "mem_ratio": round(fs.factor_values / max(fs.nnz, 1), 3),
+        "factor_breakdown_ms": {"levels": [round(fs.factor_level_ms[l], 2) for l in range(fs.levels)],
+                                "last_level_ilut": round(fs.ilut_ms, 2)},
+        "spmv_lanes": fs.spmv_lanes,
         "spmv_GBps": per_class["spmv"]["GBps"],
         "apply_GBps": per_class["apply"]["GBps"],
         "kernels": per_class,

@@ -24,7 +24,7 @@ namespace {
 constexpr int kIlutThreads = 256;
 constexpr int kMaxRowBlocks = 1024;  // largest block list of one working row
 constexpr int kUStage = 1024;        // values of one LDS tile of U row k
-constexpr int kCheckEvery = 8;       // ILUT waves between host checks
+constexpr int kCheckEvery = 16;      // ILUT waves between host checks
 constexpr int kIlutGrid = 1024;      // workgroups of every ILUT launch
 constexpr int kGatherBlocks = 256;   // workgroups of the gather kernel
 
@@ -750,9 +750,11 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
                     capv_pool, err, lvl, moved.p, lds);
                 VB_LAUNCH_CHECK();
             }
-            std::vector<int> hc, herr;
-            to_host(hc, cnt.p, 6, s);
-            to_host(herr, err, 4, s);
+            // both records come back with one synchronization
+            std::vector<int> hc(6), herr(4);
+            VB_HIP(hipMemcpyAsync(hc.data(), cnt.p, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+            VB_HIP(hipMemcpyAsync(herr.data(), err, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+            VB_HIP(hipStreamSynchronize(s));
             code = herr[0];
             eblock = herr[2];
             if (code != 0) break;

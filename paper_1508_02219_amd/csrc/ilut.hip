@@ -37,8 +37,8 @@ struct IlutLds {
 };
 template <class T>
 size_t ilut_lds_bytes(const IlutLds &l) {
-    size_t b = sizeof(T) * ((size_t)2 * l.maxm * l.maxm + l.ustage) + sizeof(int) * ((size_t)2 * l.hcap + 6 * l.rbcap + l.maxm) +
-               (size_t)l.rbcap;
+    size_t b = sizeof(T) * ((size_t)2 * l.maxm * l.maxm + l.ustage) +
+               sizeof(int) * ((size_t)2 * l.hcap + 6 * l.rbcap + l.maxm + l.ustage) + (size_t)l.rbcap;
     return (b + 15) & ~(size_t)15;
 }
 
@@ -70,6 +70,78 @@ __device__ inline void h_insert(int *keys, int *vals, unsigned hmask, int key, i
         if (old == -1 || old == key) { vals[h] = val; return; }
         h = (h + 1) & hmask;
     }
+}
+
+// Multiplier solve e <- e U^{-1} L^{-1} P for a pivot block of size MK held in LDS: the
+// same operations in the same order as the generic row solves, with the row kept in
+// registers so that only the (independent) loads of the LU factors remain in LDS.
+template <class T, int MK>
+__device__ inline void mult_solve_reg(const T *lu, const int *piv, T *e) {
+    T x[MK];
+#pragma unroll
+    for (int c = 0; c < MK; ++c) x[c] = e[c];
+#pragma unroll
+    for (int c = 0; c < MK; ++c) {
+        T s = x[c];
+#pragma unroll
+        for (int q = 0; q < c; ++q) s = s - x[q] * lu[q * MK + c];
+        x[c] = s / lu[c * MK + c];
+    }
+#pragma unroll
+    for (int c = MK - 1; c >= 0; --c) {
+        T s = x[c];
+#pragma unroll
+        for (int q = c + 1; q < MK; ++q) s = s - x[q] * lu[q * MK + c];
+        x[c] = s;
+    }
+    // row interchanges, last pivot first, as selects over the register array
+#pragma unroll
+    for (int k = MK - 1; k >= 0; --k) {
+        const int pk = piv[k];
+        const T xk = x[k];
+        T xp = xk;
+#pragma unroll
+        for (int j = 0; j < MK; ++j) xp = j == pk ? x[j] : xp;
+#pragma unroll
+        for (int j = 0; j < MK; ++j) x[j] = j == pk ? xk : x[j];
+        x[k] = xp;
+    }
+#pragma unroll
+    for (int c = 0; c < MK; ++c) e[c] = x[c];
+}
+template <class T>
+__device__ inline void mult_solve(int mk, const T *lu, const int *piv, T *e) {
+    switch (mk) {
+        case 1: mult_solve_reg<T, 1>(lu, piv, e); return;
+        case 2: mult_solve_reg<T, 2>(lu, piv, e); return;
+        case 3: mult_solve_reg<T, 3>(lu, piv, e); return;
+        case 4: mult_solve_reg<T, 4>(lu, piv, e); return;
+        case 5: mult_solve_reg<T, 5>(lu, piv, e); return;
+        default:
+            dev_row_solve_u<T>(mk, lu, e, 1);
+            dev_row_solve_lp<T>(mk, lu, piv, e, 1);
+    }
+}
+// drop rule ||B||_F / (m n) < t for a contiguous row-major block: the squares are summed in
+// index order like the generic test, with the loads issued four at a time
+template <class T>
+__device__ inline bool drop_contig(int m, int n, const T *b, double t) {
+    const int cnt = m * n;
+    T s = T(0);
+    int q = 0;
+    for (; q + 4 <= cnt; q += 4) {
+        const T v0 = b[q], v1 = b[q + 1], v2 = b[q + 2], v3 = b[q + 3];
+        s = s + v0 * v0;
+        s = s + v1 * v1;
+        s = s + v2 * v2;
+        s = s + v3 * v3;
+    }
+    for (; q < cnt; ++q) {
+        const T v = b[q];
+        s = s + v * v;
+    }
+    const T thr = T(t) * T(cnt);
+    return s < thr * thr;
 }
 
 // One dependency wave of the block ILUT: one workgroup per row of the input list.
@@ -104,12 +176,14 @@ __device__ void ilut_row(
     int *s_uoff = s_uc0 + lds.rbcap;                //   offsets of the matching blocks of w,
     int *s_un = s_uoff + lds.rbcap;                 //   block widths
     int *s_piv = s_un + lds.rbcap;                  // [maxm]
-    unsigned char *l_est = (unsigned char *)(s_piv + lds.maxm);  // [rbcap] 0 pending, 1 eliminated,
-                                                                 // 2 dropped (3/4: kept L/U)
+    int *s_cmap = s_piv + lds.maxm;                 // [ustage] per column of U row k: w offset
+                                                    //   of the column (<< 6) | block width
+    unsigned char *l_est = (unsigned char *)(s_cmap + lds.ustage);  // [rbcap] 0 pending, 1 eliminated,
+                                                                    // 2 dropped (3/4: kept L/U)
     const unsigned hmask = (unsigned)lds.hcap - 1u;
     const int kRowCap = lds.rbcap;
-    __shared__ int s_nb, s_used, s_last, s_status, s_min, s_flag, s_stop, s_ek, s_nb0;
-    __shared__ IlutRowRec s_rk;
+    __shared__ int s_nb, s_used, s_last, s_status, s_stop, s_nb0;
+    __shared__ int s_wmin[kIlutThreads / 64];
     __shared__ int s_lc, s_lw, s_uc, s_uw;
     __shared__ int64_t s_lb, s_lv, s_ub, s_uv;
     const int t = threadIdx.x;
@@ -123,6 +197,8 @@ __device__ void ilut_row(
     int *offs = woffs + B0;
     unsigned char *est = west + B0;
     T *w = wvals + V0;
+    // the column map packs a w offset with the block width (6 bits)
+    const bool use_map = CV < ((int64_t)1 << 25);
     if (t == 0) {
         RowState r = rs[i];
         s_nb = r.nb;
@@ -178,78 +254,78 @@ __device__ void ilut_row(
     for (int e = t; e < s_nb; e += kIlutThreads) h_insert(hkeys, hvals, hmask, l_cols[e], e);
     __syncthreads();
 
+    // the last eliminated column, kept by every thread (all threads take the same k)
+    int last = s_last;
     for (;;) {
-        if (t == 0) s_min = INT_MAX;
-        __syncthreads();
         {
+            // next column to eliminate: the smallest pending column left of the diagonal;
+            // one slot per wavefront, so no reset (and no barrier for it) is needed
             int mine = INT_MAX;
             for (int e = t; e < s_nb; e += kIlutThreads) {
                 const int K = l_cols[e];
-                if (K < i && K > s_last && l_est[e] == 0 && K < mine) mine = K;
+                if (K < i && K > last && l_est[e] == 0 && K < mine) mine = K;
             }
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
                 const int o = __shfl_xor(mine, off, 64);
                 mine = o < mine ? o : mine;
             }
-            if ((t & 63) == 0 && mine != INT_MAX) atomicMin(&s_min, mine);
+            if ((t & 63) == 0) s_wmin[t >> 6] = mine;
         }
         __syncthreads();
-        const int k = s_min;
+        int k = s_wmin[0];
+#pragma unroll
+        for (int q = 1; q < kIlutThreads / 64; ++q) k = s_wmin[q] < k ? s_wmin[q] : k;
         if (k == INT_MAX) break;
-        if (t == 0) {
-            // row k is usable only if an earlier launch finished it (its record is read
-            // together with the flag and used only then)
-            const int dk = done[k];
-            const IlutRowRec r = rec[k];
-            s_flag = (dk > 0 && dk < launch) ? 1 : 0;
-            if (s_flag) {
-                // the finished row must describe ranges inside the pools
-                const int mk0 = r.m;
-                int e0 = h_find(hkeys, hvals, hmask, k);
-                bool ok = e0 >= 0 && e0 < s_nb && r.uc >= 0 && r.uc <= kRowCap && r.ub >= 0 &&
-                          r.ub + r.uc <= capb_pool && r.uw >= 0 && r.uv >= 0 && r.uv + (int64_t)mk0 * r.uw <= capv_pool &&
-                          mk0 >= 1 && mk0 <= lds.maxm && r.rbeg == rb[k] && r.lu0 >= 0;
-                if (!ok) {
-                    dev_set_error(err, VBARMS_ERR_HIP, lvl, i);
-                    s_flag = 2;
+        // Row k is usable only if an earlier launch finished it.  Every thread reads the flag
+        // and the record itself: a row finished in an earlier launch is read the same by
+        // all, and any other value (0, or this launch) means "not usable" to all, so the
+        // decision is uniform without a broadcast.
+        const int dk = done[k];
+        const IlutRowRec rk = rec[k];
+        const int ek = h_find(hkeys, hvals, hmask, k);
+        if (!(dk > 0 && dk < launch)) {
+            // not finished yet: save the state of the list (the columns and offsets of
+            // entries loaded at the start of this visit are unchanged)
+            for (int e = t; e < s_nb; e += kIlutThreads) {
+                if (e >= s_nb0) {
+                    cols[e] = l_cols[e];
+                    offs[e] = l_offs[e];
                 }
-                s_ek = e0;
-                s_rk = r;
+                est[e] = l_est[e];
             }
-        }
-        __syncthreads();
-        if (s_flag != 1) {
-            if (s_flag == 0) {
-                // not finished yet: save the state of the list (the columns and offsets of
-                // entries loaded at the start of this visit are unchanged)
-                for (int e = t; e < s_nb; e += kIlutThreads) {
-                    if (e >= s_nb0) {
-                        cols[e] = l_cols[e];
-                        offs[e] = l_offs[e];
-                    }
-                    est[e] = l_est[e];
-                }
-                if (t == 0) {
-                    rs[i] = RowState{s_nb, s_used, s_last, 1};
-                    nbytes += 9ull * s_nb + 24;
-                    // wait on row k; everything written here is read in a later launch
-                    wait_on[i] = k;
-                    wait_out[atomicAdd(cnt_wait_out, 1)] = i;
-                }
+            if (t == 0) {
+                rs[i] = RowState{s_nb, s_used, last, 1};
+                nbytes += 8ull * (s_nb - s_nb0) + s_nb + 24;
+                // wait on row k; everything written here is read in a later launch
+                wait_on[i] = k;
+                wait_out[atomicAdd(cnt_wait_out, 1)] = i;
+                atomicAdd(moved, nbytes);
             }
-            if (t == 0) atomicAdd(moved, nbytes);
             return;
         }
-        const int ek = s_ek;
-        const IlutRowRec rk = s_rk;
         const int mk = rk.m;
         const int UW = rk.uw;
-        // stage the pivot-block LU of row k, its pivots, the multiplier block and U row k
-        // (values and block lists); all these loads are independent of each other
         {
-            const T *dk = dl + rk.lu0;
-            for (int e = t; e < mk * mk; e += kIlutThreads) s_lu[e] = dk[e];
+            // the finished row must describe ranges inside the pools
+            const bool ok = ek >= 0 && ek < s_nb && rk.uc >= 0 && rk.uc <= kRowCap && rk.ub >= 0 &&
+                            rk.ub + rk.uc <= capb_pool && UW >= 0 && rk.uv >= 0 &&
+                            rk.uv + (int64_t)mk * UW <= capv_pool && mk >= 1 && mk <= lds.maxm &&
+                            rk.rbeg == rb[k] && rk.lu0 >= 0;
+            if (!ok) {
+                if (t == 0) {
+                    dev_set_error(err, VBARMS_ERR_HIP, lvl, i);
+                    atomicAdd(moved, nbytes);
+                }
+                return;
+            }
+        }
+        const int TW = lds.ustage / mk;
+        // stage the pivot-block LU of row k, its pivots, the multiplier block, U row k's
+        // block lists and the first tile of its values; all these loads are independent
+        {
+            const T *dkp = dl + rk.lu0;
+            for (int e = t; e < mk * mk; e += kIlutThreads) s_lu[e] = dkp[e];
             for (int q = t; q < mk; q += kIlutThreads) s_piv[q] = dl_piv[rk.rbeg + q];
             const T *Mg = w + l_offs[ek];
             for (int e = t; e < m * mk; e += kIlutThreads) s_M[e] = Mg[e];
@@ -257,27 +333,27 @@ __device__ void ilut_row(
                 s_ucol[b] = uci[rk.ub + b];
                 s_uc0[b] = uco[rk.ub + b];
             }
+            const int tw = UW < TW ? UW : TW;
+            for (int e = t; e < mk * tw; e += kIlutThreads) {
+                const int q = e / tw, cc = e - q * tw;
+                s_U[q * tw + cc] = uv[rk.uv + (int64_t)q * UW + cc];
+            }
         }
         __syncthreads();
-        if (t < m) {
-            dev_row_solve_u<T>(mk, s_lu, s_M + t * mk, 1);
-            dev_row_solve_lp<T>(mk, s_lu, s_piv, s_M + t * mk, 1);
-        }
+        if (t < m) mult_solve<T>(mk, s_lu, s_piv, s_M + t * mk);
         __syncthreads();
+        // every thread evaluates the drop test on the same LDS block in the same order
+        const bool dropped = drop_contig<T>(m, mk, s_M, droptol);
         if (t == 0) {
-            s_flag = dev_drop<T>(m, mk, s_M, mk, droptol);
             // readiness and record of row k, its pivot block, the multiplier in and out
             nbytes += 68ull + (unsigned long long)S * mk * mk + 4ull * mk + 2ull * S * m * mk;
             // U row k with its block lists, and the read-modify-write of the updated blocks
-            if (!s_flag) nbytes += (unsigned long long)S * mk * UW + 8ull * rk.uc + 2ull * S * m * UW;
+            if (!dropped) nbytes += (unsigned long long)S * mk * UW + 8ull * rk.uc + 2ull * S * m * UW;
         }
-        __syncthreads();
-        if (s_flag) {
-            if (t == 0) {
-                l_est[ek] = 2;
-                s_last = k;
-            }
-            __syncthreads();
+        if (dropped) {
+            // the scan skips column k (k <= last), so the state byte needs no barrier here
+            if (t == 0) l_est[ek] = 2;
+            last = k;
             continue;
         }
         {
@@ -298,7 +374,10 @@ __device__ void ilut_row(
             s_un[b] = nJ;
             const int e0 = h_find(hkeys, hvals, hmask, J);
             if (e0 >= 0) {
-                s_uoff[b] = l_offs[e0];
+                const int off = l_offs[e0];
+                s_uoff[b] = off;
+                if (use_map)
+                    for (int q = 0; q < nJ && s_uc0[b] + q < lds.ustage; ++q) s_cmap[s_uc0[b] + q] = ((off + q) << 6) | nJ;
                 continue;
             }
             int e = atomicAdd(&s_nb, 1);
@@ -312,34 +391,75 @@ __device__ void ilut_row(
             l_offs[e] = off;
             l_est[e] = 0;
             s_uoff[b] = off;
+            if (use_map)
+                for (int q = 0; q < nJ && s_uc0[b] + q < lds.ustage; ++q) s_cmap[s_uc0[b] + q] = ((off + q) << 6) | nJ;
             for (int q = 0; q < m * nJ; ++q) w[off + q] = T(0);
             h_insert(hkeys, hvals, hmask, J, e);
         }
         __syncthreads();
-        if (s_stop) return;
+        if (s_stop) {
+            if (t == 0) atomicAdd(moved, nbytes);
+            return;
+        }
         // w_J -= M U_kJ for every block J of U row k; U row k is staged in LDS one tile of
-        // columns at a time and the threads share the (row, column) pairs of the tile
-        const int TW = lds.ustage / mk;
+        // columns at a time (the first tile with the block lists) and the threads share the
+        // (row, column) pairs of the tile
         for (int c0 = 0; c0 < UW; c0 += TW) {
             const int tw = UW - c0 < TW ? UW - c0 : TW;
-            for (int e = t; e < mk * tw; e += kIlutThreads) {
-                const int q = e / tw, cc = e - q * tw;
-                s_U[q * tw + cc] = uv[rk.uv + (int64_t)q * UW + c0 + cc];
+            if (c0 > 0) {
+                __syncthreads();  // the previous tile is consumed
+                for (int e = t; e < mk * tw; e += kIlutThreads) {
+                    const int q = e / tw, cc = e - q * tw;
+                    s_U[q * tw + cc] = uv[rk.uv + (int64_t)q * UW + c0 + cc];
+                }
+                __syncthreads();
             }
-            __syncthreads();
-            for (int e = t; e < m * tw; e += kIlutThreads) {
-                const int r = e / tw, cc = e - r * tw, c = c0 + cc;
-                const int b = (int)dev_floor32(s_uc0, 0, rk.uc, c);
-                const int nJ = s_un[b];
-                T *wj = w + s_uoff[b] + (c - s_uc0[b]) + r * nJ;
-                T acc = *wj;
-                for (int q = 0; q < mk; ++q) acc = acc - s_M[r * mk + q] * s_U[q * tw + cc];
-                *wj = acc;
+            // each thread takes up to four (row, column) pairs at a time and loads their w
+            // values before it stores any, so the loads are in flight together (the pairs
+            // are distinct entries of w)
+            const int tot = m * tw;
+            for (int e0 = 0; e0 < tot; e0 += 4 * kIlutThreads) {
+                T *wq[4];
+                T val[4];
+                int rq[4], cq[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * kIlutThreads + t;
+                    wq[u] = nullptr;
+                    val[u] = T(0);
+                    rq[u] = cq[u] = 0;
+                    if (e < tot) {
+                        const int r = e / tw, cc = e - r * tw, c = c0 + cc;
+                        int base, nJ;
+                        if (use_map && c < lds.ustage) {
+                            const int code = s_cmap[c];
+                            base = code >> 6;
+                            nJ = code & 63;
+                        } else {
+                            const int b = (int)dev_floor32(s_uc0, 0, rk.uc, c);
+                            nJ = s_un[b];
+                            base = s_uoff[b] + (c - s_uc0[b]);
+                        }
+                        wq[u] = w + base + r * nJ;
+                        rq[u] = r;
+                        cq[u] = cc;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (wq[u]) val[u] = *wq[u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!wq[u]) continue;
+                    T acc = val[u];
+                    for (int q = 0; q < mk; ++q) acc = acc - s_M[rq[u] * mk + q] * s_U[q * tw + cq[u]];
+                    *wq[u] = acc;
+                }
             }
-            __syncthreads();
         }
-        if (t == 0) s_last = k;
-        __syncthreads();
+        // the barrier after the next scan orders these updates before any later read of w
+        // and before the staging buffers are overwritten
+        last = k;
     }
 
     // finalize row i: pivot block, dropped upper blocks, output to the pools
@@ -368,7 +488,7 @@ __device__ void ilut_row(
         int K = l_cols[e];
         int nK = rb[K + 1] - rb[K];
         if (K < i) l_est[e] = l_est[e] == 1 ? 3 : 0;
-        else if (K > i) l_est[e] = dev_drop<T>(m, nK, w + l_offs[e], nK, droptol) ? 0 : 4;
+        else if (K > i) l_est[e] = drop_contig<T>(m, nK, w + l_offs[e], droptol) ? 0 : 4;
         else l_est[e] = 0;
     }
     __syncthreads();
@@ -420,7 +540,7 @@ __device__ void ilut_row(
     }
     if (t == 0) {
         rec[i] = IlutRowRec{s_lb, s_lv, s_ub, s_uv, s_lc, s_lw, s_uc, s_uw, dl_off[i], rb[i], m};
-        rs[i] = RowState{s_nb, s_used, s_last, 2};
+        rs[i] = RowState{s_nb, s_used, last, 2};
         done[i] = launch;
         atomicAdd(nfinished, 1);
         // pivot block in and its LU out, kept blocks copied to the pools, the records

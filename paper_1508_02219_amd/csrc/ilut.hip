@@ -144,6 +144,30 @@ __device__ inline bool drop_contig(int m, int n, const T *b, double t) {
     return s < thr * thr;
 }
 
+// Copies a rows x tw tile (row stride ld in global memory) to LDS (row stride tw).  Each
+// thread issues up to four loads before it stores any, so the loads are in flight together.
+template <class T>
+__device__ inline void stage_tile(T *dst, const T *src, int64_t ld, int rows, int tw, int t) {
+    const int tot = rows * tw;
+    for (int e0 = 0; e0 < tot; e0 += 4 * kIlutThreads) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kIlutThreads + t;
+            v[u] = T(0);
+            if (e < tot) {
+                const int q = e / tw, cc = e - q * tw;
+                v[u] = src[(int64_t)q * ld + cc];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kIlutThreads + t;
+            if (e < tot) dst[e] = v[u];
+        }
+    }
+}
+
 // One dependency wave of the block ILUT: one workgroup per row of the input list.
 //
 // The row's block list (column, value offset, state) lives in LDS for the launch and in
@@ -224,33 +248,69 @@ __device__ void ilut_row(
     __syncthreads();
     if (s_stop) return;
     if (s_status == 0) {
-        // first visit: row i of A, one list entry per block, blocks stored contiguously
+        // first visit: row i of A, one list entry per block, blocks stored contiguously;
+        // the first panel columns of its blocks also go to s_uc0 for the copy below
         const int64_t b0 = rp[i];
         for (int e = t; e < s_nb; e += kIlutThreads) {
+            const int c0 = co[b0 + e];
             l_cols[e] = ci[b0 + e];
-            l_offs[e] = m * co[b0 + e];
+            l_offs[e] = m * c0;
             l_est[e] = 0;
-        }
-        const int64_t W = wp[i + 1] - wp[i];
-        const T *A = av + vp[i];
-        for (int64_t c = t; c < W; c += kIlutThreads) {
-            int64_t b = dev_floor32(co, b0, rp[i + 1], (int)c);
-            int nJ = (b + 1 < rp[i + 1] ? co[b + 1] : (int)W) - co[b];
-            int local = (int)(c - co[b]);
-            int off = m * co[b];
-            for (int r = 0; r < m; ++r) w[off + r * nJ + local] = A[r * W + c];
+            s_uc0[e] = c0;
         }
     } else {
-        for (int e = t; e < s_nb; e += kIlutThreads) {
-            l_cols[e] = cols[e];
-            l_offs[e] = offs[e];
-            l_est[e] = est[e];
+        // resumed row: the saved list, four entries per thread loaded before any is stored
+        for (int e0 = 0; e0 < s_nb; e0 += 4 * kIlutThreads) {
+            int cv[4], ov[4];
+            unsigned char sv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * kIlutThreads + t;
+                cv[u] = ov[u] = 0;
+                sv[u] = 0;
+                if (e < s_nb) {
+                    cv[u] = cols[e];
+                    ov[u] = offs[e];
+                    sv[u] = est[e];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * kIlutThreads + t;
+                if (e < s_nb) {
+                    l_cols[e] = cv[u];
+                    l_offs[e] = ov[u];
+                    l_est[e] = sv[u];
+                }
+            }
         }
     }
     for (int h = t; h < lds.hcap; h += kIlutThreads) hkeys[h] = -1;
     // entries below s_nb0 are already in the row's global list (not on a first visit)
     if (t == 0) s_nb0 = s_status == 0 ? 0 : s_nb;
     __syncthreads();
+    if (s_status == 0) {
+        // the dense blocks of row i of A go to w block by block (each block row-major);
+        // the block of a panel column is found in LDS, and the m values of a column are
+        // loaded (eight at a time) before they are stored
+        const int nA = s_nb;
+        const int64_t W = wp[i + 1] - wp[i];
+        const T *A = av + vp[i];
+        for (int64_t c = t; c < W; c += kIlutThreads) {
+            const int b = (int)dev_floor32(s_uc0, 0, nA, (int)c);
+            const int nJ = (b + 1 < nA ? s_uc0[b + 1] : (int)W) - s_uc0[b];
+            const int local = (int)(c - s_uc0[b]);
+            T *dst = w + m * s_uc0[b] + local;
+            for (int r0 = 0; r0 < m; r0 += 8) {
+                T v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = r0 + u < m ? A[(int64_t)(r0 + u) * W + c] : T(0);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (r0 + u < m) dst[(r0 + u) * nJ] = v[u];
+            }
+        }
+    }
     for (int e = t; e < s_nb; e += kIlutThreads) h_insert(hkeys, hvals, hmask, l_cols[e], e);
     __syncthreads();
 
@@ -333,11 +393,7 @@ __device__ void ilut_row(
                 s_ucol[b] = uci[rk.ub + b];
                 s_uc0[b] = uco[rk.ub + b];
             }
-            const int tw = UW < TW ? UW : TW;
-            for (int e = t; e < mk * tw; e += kIlutThreads) {
-                const int q = e / tw, cc = e - q * tw;
-                s_U[q * tw + cc] = uv[rk.uv + (int64_t)q * UW + cc];
-            }
+            stage_tile<T>(s_U, uv + rk.uv, UW, mk, UW < TW ? UW : TW, t);
         }
         __syncthreads();
         if (t < m) mult_solve<T>(mk, s_lu, s_piv, s_M + t * mk);
@@ -408,10 +464,7 @@ __device__ void ilut_row(
             const int tw = UW - c0 < TW ? UW - c0 : TW;
             if (c0 > 0) {
                 __syncthreads();  // the previous tile is consumed
-                for (int e = t; e < mk * tw; e += kIlutThreads) {
-                    const int q = e / tw, cc = e - q * tw;
-                    s_U[q * tw + cc] = uv[rk.uv + (int64_t)q * UW + c0 + cc];
-                }
+                stage_tile<T>(s_U, uv + rk.uv + c0, UW, mk, tw, t);
                 __syncthreads();
             }
             // each thread takes up to four (row, column) pairs at a time and loads their w

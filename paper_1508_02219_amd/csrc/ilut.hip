@@ -25,6 +25,8 @@ constexpr int kIlutThreads = 256;
 constexpr int kMaxRowBlocks = 1024;  // largest block list of one working row
 constexpr int kUStage = 1024;        // values of one LDS tile of U row k
 constexpr int kCheckEvery = 16;      // ILUT waves between host checks
+constexpr int kStepCap = 8;          // elimination steps a row takes per launch (the smallest
+                                     // ready row is exempt)
 constexpr int kIlutGrid = 1024;      // workgroups of every ILUT launch
 constexpr int kGatherBlocks = 256;   // workgroups of the gather kernel
 
@@ -180,7 +182,7 @@ __device__ inline void stage_tile(T *dst, const T *src, int64_t ld, int rows, in
 // the gather kernel of a later launch returns it to the ready list once k has finished.
 template <class T>
 __device__ void ilut_row(
-    const int i, int launch, int p, int *wait_out, int *cnt_wait_out, int *wait_on, int *nfinished,
+    const int i, int launch, int min_ready, int p, int *wait_out, int *cnt_wait_out, int *wait_on, int *nfinished,
     const int *rb, const int64_t *rp, const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av,
     double droptol, int *done, RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols, int *woffs,
     unsigned char *west, T *wvals, T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec, int *lci, int *lco,
@@ -316,7 +318,7 @@ __device__ void ilut_row(
 
     // the last eliminated column, kept by every thread (all threads take the same k)
     int last = s_last;
-    for (;;) {
+    for (int nstep = 0;; ++nstep) {
         {
             // next column to eliminate: the smallest pending column left of the diagonal;
             // one slot per wavefront, so no reset (and no barrier for it) is needed
@@ -344,8 +346,13 @@ __device__ void ilut_row(
         const int dk = done[k];
         const IlutRowRec rk = rec[k];
         const int ek = h_find(hkeys, hvals, hmask, k);
-        if (!(dk > 0 && dk < launch)) {
-            // not finished yet: save the state of the list (the columns and offsets of
+        // A row that has taken kStepCap steps in this launch stops here as if row k were
+        // unfinished (the gather returns it to the ready list at once if k is finished): a
+        // wave then lasts a bounded number of steps instead of the longest backlog of ready
+        // eliminations.  The smallest ready row is exempt, so every launch still finishes it.
+        const bool capped = nstep >= kStepCap && i != min_ready;
+        if (capped || !(dk > 0 && dk < launch)) {
+            // not usable now: save the state of the list (the columns and offsets of
             // entries loaded at the start of this visit are unchanged)
             for (int e = t; e < s_nb; e += kIlutThreads) {
                 if (e >= s_nb0) {
@@ -621,7 +628,7 @@ __device__ inline int wave_append(bool take, int *counter) {
 
 __global__ void __launch_bounds__(256) k_ilut_gather(const int *wait_in, const int *cnt_wait_in, const int *wait_on,
                                                      const int *done, int *ready, int *cnt_ready, int *wait_out,
-                                                     int *cnt_wait_out) {
+                                                     int *cnt_wait_out, int *min_ready) {
     const int n = *cnt_wait_in;
     const int stride = gridDim.x * blockDim.x;
     // every lane of a wavefront takes part in each round, so the ballots see all of them
@@ -640,6 +647,14 @@ __global__ void __launch_bounds__(256) k_ilut_gather(const int *wait_in, const i
             if (rdy) ready[pr] = i;
             else wait_out[pw] = i;
         }
+        // smallest row moved to the ready list (one atomic per wavefront)
+        int mn = e < n && rdy ? i : INT_MAX;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const int o = __shfl_xor(mn, off, 64);
+            mn = o < mn ? o : mn;
+        }
+        if ((threadIdx.x & 63) == 0 && mn != INT_MAX) atomicMin(min_ready, mn);
     }
 }
 
@@ -649,7 +664,8 @@ __global__ void __launch_bounds__(256) k_ilut_gather(const int *wait_in, const i
 // both last read by launch L-1.
 template <class T>
 __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
-    int launch, int p, const int *ready, const int *cnt_ready, int *cnt_ready_clear, int *wait_out,
+    int launch, int p, const int *ready, const int *cnt_ready, int *cnt_ready_clear, const int *min_ready_in,
+    int *min_ready_clear, int *wait_out,
     int *cnt_wait_out, int *cnt_wait_clear, int *wait_on, int *nfinished, const int *rb, const int64_t *rp,
     const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av, double droptol, int *done,
     RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols, int *woffs, unsigned char *west, T *wvals,
@@ -659,10 +675,12 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *cnt_ready_clear = 0;
         *cnt_wait_clear = 0;
+        *min_ready_clear = INT_MAX;
     }
     const int nin = *cnt_ready;
+    const int min_ready = *min_ready_in;
     for (int slot = blockIdx.x; slot < nin; slot += gridDim.x) {
-        ilut_row<T>(ready[slot], launch, p, wait_out, cnt_wait_out, wait_on, nfinished, rb, rp, ci, co, wp, vp, av,
+        ilut_row<T>(ready[slot], launch, min_ready, p, wait_out, cnt_wait_out, wait_on, nfinished, rb, rp, ci, co, wp, vp, av,
                     droptol, done, rs, boff, voff, wcols, woffs, west, wvals, dl, dl_off, dl_piv, rec, lci, lco, lv, uci,
                     uco, uv, cursors, capb_pool, capv_pool, err, lvl, moved, lds);
         __syncthreads();
@@ -889,7 +907,7 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         lds.ustage = kUStage;
         const size_t lds_bytes = ilut_lds_bytes<T>(lds);
         // cnt: three rotating waiting-list counters, two ready counters, finished rows
-        DBuf<int> done(p), waits(2 * (size_t)p), ready(p), wait_on(p), cnt(6);
+        DBuf<int> done(p), waits(2 * (size_t)p), ready(p), wait_on(p), cnt(8);
         DBuf<unsigned long long> moved(1);
         fill_val<unsigned long long>(moved.p, 0ull, 1, s);
         VB_HIP(hipMemsetAsync(rs.p, 0, sizeof(RowState) * p, s));
@@ -897,26 +915,30 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         fill_i32(done.p, 0, p, s);
         fill_i32(wait_on.p, -1, p, s);
         iota_i32(waits.p + p, p, s);  // waiting list of launch 1 (odd launches read the second list)
-        const int cnt0[6] = {0, p, 0, 0, 0, 0};
-        to_device(cnt.p, cnt0, 6, s);
+        // waiting counts (3), ready counts (2), finished rows, smallest ready row (2)
+        const int cnt0[8] = {0, p, 0, 0, 0, 0, INT_MAX, INT_MAX};
+        to_device(cnt.p, cnt0, 8, s);
         VB_HIP(hipMemsetAsync(err, 0, 4 * sizeof(int), s));
-        int *cw = cnt.p, *cr = cnt.p + 3, *nfin = cnt.p + 5;
+        int *cw = cnt.p, *cr = cnt.p + 3, *nfin = cnt.p + 5, *mr = cnt.p + 6;
         const unsigned grid = (unsigned)std::min(p, kIlutGrid);
         int finished = 0, launch = 0, code = 0, eblock = 0;
         while (finished < p) {
             // every launch finishes at least one row: the smallest unfinished row depends only
-            // on rows finished in earlier launches, so the gather always finds it ready
+            // on rows finished in earlier launches, so the gather always finds it ready, and as
+            // the smallest ready row it is exempt from the step cap
             if (launch > p + kCheckEvery) fail(VBARMS_ERR_HIP, "block ILUT made no progress");
             for (int q = 0; q < kCheckEvery; ++q) {
                 ++launch;
                 const int *w_in = waits.p + (size_t)(launch & 1) * p;
                 int *w_out = waits.p + (size_t)((launch + 1) & 1) * p;
                 k_ilut_gather<<<kGatherBlocks, 256, 0, s>>>(w_in, cw + launch % 3, wait_on.p, done.p, ready.p,
-                                                            cr + launch % 2, w_out, cw + (launch + 1) % 3);
+                                                            cr + launch % 2, w_out, cw + (launch + 1) % 3,
+                                                            mr + launch % 2);
                 VB_LAUNCH_CHECK();
                 KScope ks(VBARMS_K_ILUT, 0.0, s);
                 k_ilut_wave<T><<<grid, kIlutThreads, lds_bytes, s>>>(
-                    launch, p, ready.p, cr + launch % 2, cr + (launch + 1) % 2, w_out, cw + (launch + 1) % 3,
+                    launch, p, ready.p, cr + launch % 2, cr + (launch + 1) % 2, mr + launch % 2, mr + (launch + 1) % 2,
+                    w_out, cw + (launch + 1) % 3,
                     cw + (launch + 2) % 3, wait_on.p, nfin, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p,
                     droptol, done.p, rs.p, boff.p, voff.p, wcols.p, woffs.p, west.p, wvals.p, last.dl.p,
                     last.dl_off.p, last.dl_piv.p, rec.p, lci.p, lco.p, lv.p, uci.p, uco.p, uv.p, cursors.p, capb_pool,

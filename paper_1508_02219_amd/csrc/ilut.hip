@@ -788,8 +788,20 @@ __global__ void __launch_bounds__(kSweepThreads) k_trsv_level(const SweepRow *ro
     const int *c = sc + R.w0;
     double acc = 0.0;
     if (grp < m) {
+        // four columns per lane at a time: their indices, values and x entries are loaded
+        // before any is used; the sum keeps the column order of the plain loop
         const T *a = v + R.v0 + (int64_t)grp * R.W;
-        for (int64_t j = gl; j < R.W; j += tg) acc += (double)a[j] * x[c[j]];
+        int64_t j = gl;
+        for (; j + 3 * tg < R.W; j += 4 * tg) {
+            const int c0 = c[j], c1 = c[j + tg], c2 = c[j + 2 * tg], c3 = c[j + 3 * tg];
+            const T a0 = a[j], a1 = a[j + tg], a2 = a[j + 2 * tg], a3 = a[j + 3 * tg];
+            const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+            acc += (double)a0 * x0;
+            acc += (double)a1 * x1;
+            acc += (double)a2 * x2;
+            acc += (double)a3 * x3;
+        }
+        for (; j < R.W; j += tg) acc += (double)a[j] * x[c[j]];
     }
     for (int off = tg / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, tg);
     if (grp < m && gl == 0) sv[grp] = b[R.r_begin + grp] - acc;

@@ -43,7 +43,7 @@ def lib():
         i32, i64, dbl = C.c_int32, C.c_int64, C.c_double
         l.orc_compress.argtypes = [C.c_int, P, P, dbl, P, P, P]
         l.orc_compress.restype = C.c_int
-        l.orc_build.argtypes = [C.c_int, P, P, P, P, P, C.c_int, C.c_int, P, C.c_int]
+        l.orc_build.argtypes = [C.c_int, P, P, P, P, P, C.c_int, C.c_int, P, C.c_int, C.c_int]
         l.orc_build.restype = P
         l.orc_free.argtypes = [P]
         l.orc_status.argtypes = [P, P, P]
@@ -125,7 +125,7 @@ class BlockMatrix:
 class Oracle:
     """Sequential FP64 VBARMS: compression result in, factors and solves out."""
 
-    def __init__(self, n, rowptr, col, val, perm, bptr, levels, droptol, drop_schur=1):
+    def __init__(self, n, rowptr, col, val, perm, bptr, levels, droptol, drop_schur=1, is_order=0):
         rp, ci, v = _csr(rowptr, col, val)
         perm = np.ascontiguousarray(perm, dtype=np.int32)
         bptr = np.ascontiguousarray(bptr, dtype=np.int32)
@@ -137,7 +137,7 @@ class Oracle:
         self.n = n
         self._keep = (rp, ci, v, perm, bptr, dt)
         self.h = lib().orc_build(n, _p(rp), _p(ci), _p(v), _p(perm), _p(bptr), len(bptr) - 1,
-                                 levels, _p(dt), drop_schur)
+                                 levels, _p(dt), drop_schur, is_order)
         el = np.zeros(1, np.int32)
         eb = np.zeros(1, np.int32)
         self.status = lib().orc_status(self.h, _p(el), _p(eb))

@@ -30,6 +30,10 @@
  *     column order, its multiplier is dropped before use if it passes R4.
  *  R6 (Eq. blockperm) every block row carries its diagonal block, zero padded if no
  *     entry of A falls there.
+ *  R7 (Sec. 3, Step 3, "weighted greedy") the weighted mode visits supernodes by
+ *     descending w_I = ||A_II||_F / sum_J ||A_IJ||_F of the scaled matrix, so rows whose
+ *     diagonal block dominates enter the independent set first; ties in ascending I.
+ *     The set is still listed in ascending supernode order in P_I.
  */
 #include <math.h>
 #include <stdint.h>
@@ -421,8 +425,43 @@ static void level_scale(olevel *L) {
     free(tmp);
 }
 
-/* Step 3 (R3): greedy independent set, natural order, on the quotient graph of A + A^T */
-static void level_indset(olevel *L, int *is_flag) {
+/* Visiting order of the weighted greedy independent set (Sec. 3, Step 3): supernodes by
+ * descending weight w_I = ||A_II||_F / sum_J ||A_IJ||_F over the blocks of row I (R7), equal
+ * weights in ascending I.  A row without a stored diagonal block has weight 0. */
+typedef struct { double w; int I; } wnode;
+static int cmp_wnode(const void *x, const void *y) {
+    const wnode *a = (const wnode *)x, *b = (const wnode *)y;
+    if (a->w > b->w) return -1;
+    if (a->w < b->w) return 1;
+    return (a->I > b->I) - (a->I < b->I);
+}
+static void weighted_order(const bmat *A, int *order) {
+    int p = A->p;
+    wnode *nodes = xmalloc(sizeof(wnode) * (size_t)(p ? p : 1));
+    for (int I = 0; I < p; ++I) {
+        int m = bm_rs(A, I);
+        double diag = 0.0, tot = 0.0;
+        for (int64_t k = A->rp[I]; k < A->rp[I + 1]; ++k) {
+            int J = A->ci[k], nJ = bm_cs(A, J);
+            const double *b = bm_blk(A, k);
+            double ss = 0.0;
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < nJ; ++c) ss += b[r * nJ + c] * b[r * nJ + c];
+            double f = sqrt(ss);
+            tot += f;
+            if (J == I) diag = f;
+        }
+        nodes[I].w = tot > 0.0 ? diag / tot : 0.0;
+        nodes[I].I = I;
+    }
+    qsort(nodes, (size_t)p, sizeof(wnode), cmp_wnode);
+    for (int q = 0; q < p; ++q) order[q] = nodes[q].I;
+    free(nodes);
+}
+
+/* Step 3 (R3): greedy independent set on the quotient graph of A + A^T, visiting the
+ * supernodes in natural order (is_order 0) or by the weights above (is_order 1) */
+static void level_indset(olevel *L, int *is_flag, int is_order) {
     const bmat *A = &L->As;
     int p = A->p;
     /* transpose pattern so that both (I,J) and (J,I) mark neighbours */
@@ -436,23 +475,27 @@ static void level_indset(olevel *L, int *is_flag) {
         for (int64_t k = A->rp[I]; k < A->rp[I + 1]; ++k) tr[f[A->ci[k]]++] = I;
     free(f);
     char *marked = xcalloc((size_t)p + 1, 1);
+    int *order = xmalloc(sizeof(int) * (size_t)(p ? p : 1));
+    if (is_order == 1) weighted_order(A, order);
+    else for (int I = 0; I < p; ++I) order[I] = I;
     for (int I = 0; I < p; ++I) is_flag[I] = 0;
-    for (int I = 0; I < p; ++I) {
+    for (int q = 0; q < p; ++q) {
+        int I = order[q];
         if (marked[I]) continue;
         is_flag[I] = 1;
         marked[I] = 1;
         for (int64_t k = A->rp[I]; k < A->rp[I + 1]; ++k) marked[A->ci[k]] = 1;
         for (int64_t k = tp[I]; k < tp[I + 1]; ++k) marked[tr[k]] = 1;
     }
-    free(tp); free(tr); free(marked);
+    free(tp); free(tr); free(marked); free(order);
 }
 
 /* Steps 3-4 on one level; produces A_{l+1} in *next */
-static int level_factor(olevel *L, double t, int drop_schur, bmat *next, int *err_block) {
+static int level_factor(olevel *L, double t, int drop_schur, int is_order, bmat *next, int *err_block) {
     const bmat *A = &L->As;
     int p = A->p;
     int *is_flag = xmalloc(sizeof(int) * (size_t)(p ? p : 1));
-    level_indset(L, is_flag);
+    level_indset(L, is_flag, is_order);
     /* P_I: independent set ascending, then the rest ascending */
     int *num = xmalloc(sizeof(int) * (size_t)(p ? p : 1));
     L->nis = 0;
@@ -689,7 +732,7 @@ void orc_free(orc_t *h);
 
 orc_t *orc_build(int n, const int64_t *rowptr, const int32_t *col, const double *val,
                  const int32_t *perm, const int32_t *bptr, int p,
-                 int levels, const double *droptol, int drop_schur) {
+                 int levels, const double *droptol, int drop_schur, int is_order) {
     orc_t *h = xcalloc(1, sizeof(orc_t));
     h->n = n; h->p = p;
     h->err_level = -1; h->err_block = -1;
@@ -710,7 +753,7 @@ orc_t *orc_build(int n, const int64_t *rowptr, const int32_t *col, const double 
         level_scale(L);
         bmat next;
         int eb = -1;
-        int st = level_factor(L, droptol[l], drop_schur, &next, &eb);
+        int st = level_factor(L, droptol[l], drop_schur, is_order, &next, &eb);
         h->nlev = l + 1;
         if (st != ORC_OK) { h->status = st; h->err_level = l; h->err_block = eb; memset(&h->last, 0, sizeof(bmat)); return h; }
         cur = next;

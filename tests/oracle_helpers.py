@@ -114,3 +114,55 @@ def node_rows_reversed(s, mode="reverse"):
     col = np.concatenate([s.col[s.rowptr[o]:s.rowptr[o + 1]] for o in order]).astype(np.int32)
     val = np.concatenate([s.val[s.rowptr[o]:s.rowptr[o + 1]] for o in order])
     return System(s.n, rowptr, col, val, s.b[order], s.node_ell, name=s.name + "-rev")
+
+
+def dense_block_ilut(a, rb, t):
+    """Block IKJ ILUT with threshold t on a dense matrix (Alg. 3 read blockwise, Sec. 3).
+
+    Written from the algorithm's definition, with none of the oracle's structure: row i is
+    the dense block row w = A_i,: ; for k = 0 .. i-1 in ascending order the multiplier
+    w_k D_k^{-1} is formed with a dense inverse of row k's (unfactored) diagonal block and
+    dropped when ||w_k||_F / (m m_k) < t, otherwise every w_j, j > k, loses w_k U_kj.
+    Blocks that are structurally absent are zero here, and a zero multiplier is always
+    dropped for t > 0, so they change nothing.  Then U_ii = w_i and the blocks w_j, j > i,
+    that pass the same test (kept when not below t) form U row i.
+
+    Returns (L, U, D, mult_ratios, u_ratios): dicts (i, k) -> multiplier, (i, j) -> U
+    block, i -> U_ii before factorization, and the ratios ||B||_F^2 / (t m n)^2 of every
+    drop decision taken on a nonzero multiplier and on a nonzero off-diagonal U candidate
+    (a ratio below 1 drops the block; callers check the margins)."""
+    p = len(rb) - 1
+    L, U, D = {}, {}, {}
+    mult_ratios, u_ratios = [], []
+
+    def blk(w, j):
+        return w[:, rb[j]:rb[j + 1]]
+
+    for i in range(p):
+        w = a[rb[i]:rb[i + 1], :].copy()
+        m = rb[i + 1] - rb[i]
+        for k in range(i):
+            wk = blk(w, k)
+            if not np.any(wk):
+                continue
+            mult = wk @ np.linalg.inv(D[k])
+            mk = rb[k + 1] - rb[k]
+            r = float(np.sum(mult * mult)) / (t * m * mk) ** 2
+            mult_ratios.append(r)
+            wk[:, :] = 0.0
+            if r < 1.0:
+                continue
+            L[(i, k)] = mult
+            for j in range(k + 1, p):
+                if (k, j) in U:
+                    w[:, rb[j]:rb[j + 1]] -= mult @ U[(k, j)]
+        D[i] = blk(w, i).copy()
+        for j in range(i + 1, p):
+            wj = blk(w, j)
+            if not np.any(wj):
+                continue
+            r = float(np.sum(wj * wj)) / (t * m * (rb[j + 1] - rb[j])) ** 2
+            u_ratios.append(r)
+            if r >= 1.0:
+                U[(i, j)] = wj.copy()
+    return L, U, D, mult_ratios, u_ratios

@@ -30,6 +30,18 @@ MUTATIONS = {
     "ilut_update_sign": ("wj[r * nJ + c] = wj[r * nJ + c] - wk[r * mk + q] * ub[q * nJ + c];",
                          "wj[r * nJ + c] = wj[r * nJ + c] + wk[r * mk + q] * ub[q * nJ + c];"),
     "ilut_keeps_dropped_multiplier": ("if (drop_block(m, mk, wk, t)) { state[k] = 2; continue; }", ""),
+    "ilut_drop_before_solve": (
+        "for (int r = 0; r < m; ++r) { row_solve_u(mk, dk, wk + r * mk); row_solve_lp(mk, dk, pk, wk + r * mk); }\n"
+        "            if (drop_block(m, mk, wk, t)) { state[k] = 2; continue; }",
+        "if (drop_block(m, mk, wk, t)) { state[k] = 2; continue; }\n"
+        "            for (int r = 0; r < m; ++r) { row_solve_u(mk, dk, wk + r * mk); row_solve_lp(mk, dk, pk, wk + r * mk); }"),
+    "ilut_u_test_square": ("if (K > i && !drop_block(m, bm_cs(A, K), acc + slot[K], t))",
+                           "if (K > i && !drop_block(m, m < bm_cs(A, K) ? m : bm_cs(A, K), acc + slot[K], t))"),
+    "ilut_u_never_dropped": ("if (K > i && !drop_block(m, bm_cs(A, K), acc + slot[K], t))",
+                             "if (K > i && (t <= 1.0 || !drop_block(m, bm_cs(A, K), acc + slot[K], t)))"),
+    "weighted_order_ascending": ("if (a->w > b->w) return -1;\n    if (a->w < b->w) return 1;",
+                                 "if (a->w > b->w) return 1;\n    if (a->w < b->w) return -1;"),
+    "weighted_order_no_diag_norm_root": ("double f = sqrt(ss);", "double f = ss;"),
     "apply_wrong_output_scale": ("x[A->rb[J] + r] = L->s2[A->rb[J] + r] * z[L->rest_rb[j] + r];",
                                  "x[A->rb[J] + r] = L->s1[A->rb[J] + r] * z[L->rest_rb[j] + r];"),
     "apply_skips_g_correction": ("yi[r] = yi[r] - gb[r * nK + q] * z[L->rest_rb[K] + q];", "yi[r] = yi[r];"),

@@ -323,6 +323,59 @@ def test_no_schur_drop_mode_keeps_all_blocks(orc):
     np.testing.assert_array_equal(d0[kept], d1[kept])
 
 
+def _weighted_greedy_bruteforce(bm):
+    """Greedy independent set on the quotient graph of A + A^T visiting block rows by
+    descending ||A_II||_F / sum_J ||A_IJ||_F (ties ascending), from the dense blocks; also
+    returns the smallest relative gap between distinct weights (to rule out near ties)."""
+    w = np.zeros(bm.p)
+    for i in range(bm.p):
+        norms = {int(bm.colidx[k]): np.linalg.norm(bm.block(k)) for k in range(bm.rowptr[i], bm.rowptr[i + 1])}
+        tot = sum(norms.values())
+        w[i] = norms.get(i, 0.0) / tot if tot > 0 else 0.0
+    order = sorted(range(bm.p), key=lambda i: (-w[i], i))
+    adj = H.quotient_adjacency(bm)
+    marked = np.zeros(bm.p, bool)
+    out = []
+    for v in order:
+        if marked[v]:
+            continue
+        out.append(v)
+        marked[v] = True
+        for u in adj[v]:
+            marked[u] = True
+    ws = np.sort(w)
+    gaps = np.diff(ws)
+    gaps = gaps[gaps > 0]
+    return np.array(sorted(out), dtype=np.int32), (gaps.min() / ws.max() if gaps.size else np.inf), adj
+
+
+@pytest.mark.parametrize("levels", [1, 3])
+@pytest.mark.parametrize("maker", ["grid", "upwind"])
+def test_weighted_independent_set_matches_bruteforce(orc, maker, levels):
+    """Sec. 3 Step 3, weighted greedy: brute force on every level, independence and
+    maximality, and a different set from the natural order on the same input."""
+    if maker == "grid":
+        s = synth.grid_system(5, 4, 4, ell=4, stencil="14rand", perturb=0.1, seed=91)
+        tau = 0.8
+    else:
+        s = synth.upwind_system(5, 4, 4, seed=92)
+        tau = 1.0
+    perm, bptr = orc.compress(s.n, s.rowptr, s.col, tau)
+    o = orc.Oracle(s.n, s.rowptr, s.col, s.val, perm, bptr, levels, 1e-3, 1, 1)
+    on = orc.Oracle(s.n, s.rowptr, s.col, s.val, perm, bptr, levels, 1e-3, 1, 0)
+    assert o.status == 0 and o.nlevels == levels
+    for lvl in range(levels):
+        As = o.matrix(orc.AS, lvl)
+        want, gap, adj = _weighted_greedy_bruteforce(As)
+        assert gap > 1e-9
+        got = o.level_is(lvl)
+        np.testing.assert_array_equal(got, want)
+        isset = set(got.tolist())
+        assert all(not (adj[v] & isset) for v in isset)
+        assert all(v in isset or (adj[v] & isset) for v in range(As.p))
+    assert not np.array_equal(o.level_is(0), on.level_is(0))
+
+
 # --------------------------------------------------------------------------------------
 # Last level block ILUT (Sec. 3, Alg. 3)
 # --------------------------------------------------------------------------------------
@@ -352,6 +405,60 @@ def test_last_level_huge_threshold_is_block_jacobi(orc):
         k = [kk for kk in range(A.rowptr[i], A.rowptr[i + 1]) if A.colidx[kk] == i][0]
         lu, piv = sla.lu_factor(A.block(k))
         np.testing.assert_allclose(dl.block(i), lu, rtol=1e-13, atol=1e-15)
+
+
+def _blocks(bm):
+    out = {}
+    for i in range(bm.p):
+        for k in range(bm.rowptr[i], bm.rowptr[i + 1]):
+            out[(i, int(bm.colidx[k]))] = bm.block(k)
+    return out
+
+
+_ILUT_CASES = {
+    # (system, levels, t): variable blocks of 1..7 unknowns; "shift" also forces row
+    # interchanges inside every pivot block; levels = 1 runs the ILUT on a Schur complement
+    "upwind-l0": (lambda: synth.upwind_system(4, 4, 3, seed=81), 0, 1e-2),
+    "upwind-l1": (lambda: synth.upwind_system(4, 4, 3, seed=81), 1, 3e-3),
+    "upwind-shift-l0": (lambda: H.node_rows_reversed(synth.upwind_system(4, 4, 3, seed=82), "shift"), 0, 1e-2),
+    "upwind-shift-l1": (lambda: H.node_rows_reversed(synth.upwind_system(4, 4, 3, seed=82), "shift"), 1, 1e-2),
+}
+
+
+@pytest.mark.parametrize("case", sorted(_ILUT_CASES))
+def test_last_level_ilut_dropping_matches_dense_bruteforce(orc, case):
+    """Block ILUT at drop tolerances that keep some multipliers and U blocks and drop
+    others (Sec. 3 drop rule inside Alg. 3): same kept sets and the same values as a dense
+    block IKJ elimination written from the definition."""
+    make, levels, t = _ILUT_CASES[case]
+    s = make()
+    o, _, _ = _oracle(orc, s, 1.0, levels, t)
+    assert o.status == 0
+    A = o.matrix(orc.LAST)
+    if levels == 0:
+        # with no reduction the ILUT input is the permuted input matrix itself
+        perm, _ = orc.compress(s.n, s.rowptr, s.col, 1.0)
+        np.testing.assert_array_equal(A.dense(), s.dense()[np.ix_(perm, perm)])
+    Lb, Ub, Db, mr, ur = H.dense_block_ilut(A.dense(), A.rb, t)
+    mr, ur = np.array(mr), np.array(ur)
+    # both kinds of decision go both ways, and none is within rounding of the threshold
+    assert np.sum(mr < 1) > 0 and np.sum(mr >= 1) > 0
+    assert np.sum(ur < 1) > 0 and np.sum(ur >= 1) > 0
+    assert np.min(np.abs(np.concatenate([mr, ur]) - 1.0)) > 1e-4
+    # variable block sizes really occur (the drop threshold scales with m n)
+    assert len(set(np.diff(A.rb).tolist())) > 3
+    Lo, Uo = _blocks(o.matrix(orc.L)), _blocks(o.matrix(orc.U))
+    assert set(Lo) == set(Lb)
+    assert set(Uo) == set(Ub)
+    for key, v in Lb.items():
+        assert np.abs(Lo[key] - v).max() <= 1e-10 * np.abs(v).max()
+    for key, v in Ub.items():
+        assert np.abs(Uo[key] - v).max() <= 1e-10 * np.abs(v).max()
+    PtL, Uu = _block_lu_parts(o.matrix(orc.DL))
+    for i in range(A.p):
+        a, b = A.rb[i], A.rb[i + 1]
+        d = (PtL @ Uu)[a:b, a:b]
+        assert np.abs(d - Db[i]).max() <= 1e-10 * np.abs(Db[i]).max()
 
 
 # --------------------------------------------------------------------------------------

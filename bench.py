@@ -1,26 +1,30 @@
 #!/usr/bin/env python3
 """Time-to-solve benchmark of the VBARMS hot path on one MI355X.
 
-Workload: 40^3 grid, 14-neighbour random stencil, 5 unknowns per node (n = 320,000,
-nnz ~ 21.9M), 10% of each block's entries removed or scaled by 1e-6 so that angle
-compression at tau = 0.8 has to rebuild the blocks; 3 levels, drop tolerance 1e-4,
-FGMRES(50) to a true relative residual of 1e-8, b = A 1.
+Default workload: 74^3 mesh nodes (405,224) on the 14-neighbour random stencil, a block of
+1 to 7 unknowns per node drawn uniformly (n = 1,619,907, nnz = 96.6M), upwind convection
+values with cell Peclet numbers LogUniform(0.1, 100); tau = 1 (exact node blocks), 4
+levels, drop tolerance 1e-4, FGMRES(60) to a true relative residual of 1e-8, b = A 1.
+`--workload grid40` runs the 40^3 five-unknown workload instead (n = 320,000, 10% block
+perturbation, tau = 0.8, 3 levels, FGMRES(50)).
 
-One step = the whole hot path from the device-resident CSR: compress (Sec. 2.1),
-factor (Sec. 3, all levels and the last-level block ILUT), solve (FGMRES with the
-preconditioner applied every iteration, Alg. 2).  W untimed steps, then K timed steps
-between device synchronizations.  During the timed steps the library records HIP events
-on its own stream around each launch class; the dominant class gives the roofline
-figure.  The oracle (CPU, FP64) solves the same system once on the host for the
-CPU-baseline figure.
+One step = the whole hot path from the device-resident CSR: compress (Sec. 2.1), factor
+(Sec. 3, all levels and the last-level block ILUT), solve (FGMRES with the
+preconditioner applied every iteration, Alg. 2).  Both precisions run the same steps:
+plain FP64, and FP32 factors with FP64 FGMRES (mixed).  For each: W untimed steps, then
+K timed steps between device synchronizations, with no instrumentation inside the timed
+region.  One further untimed step per precision records HIP events around every launch
+class for the per-kernel figures and the roofline.  The oracle (CPU, FP64) solves a
+smaller grid of the same recipe on the host for the CPU-baseline figure.
 
-Prints one JSON line.
+Prints one JSON line; `value` is the mixed-precision time-to-solve.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -30,31 +34,62 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-solve @1e-8 rel residual + SpMV/solve GB/s, mixed/learned vs FP64 plain"
 HBM_PEAK_GBPS = 8000.0
-TAU, LEVELS, DROPTOL, RESTART, TOL, MAXIT = 0.8, 3, 1e-4, 50, 1e-8, 1000
+TOL, MAXIT = 1e-8, 1000
+
+WORKLOADS = {
+    "upwind74": dict(desc="74^3 nodes, 14-neighbour random stencil, 1..7 unknowns per node, upwind "
+                          "convection (cell Peclet LogUniform(0.1, 100))",
+                     make=lambda side: __import__("paper_1508_02219_amd.synth", fromlist=["x"]).upwind_system(
+                         side, side, side, seed=3),
+                     side=74, sample_side=48, tau=1.0, levels=4, droptol=1e-4, restart=60),
+    "grid40": dict(desc="40^3 nodes, 14-neighbour random stencil, 5 unknowns per node, 10% block perturbation",
+                   make=lambda side: __import__("paper_1508_02219_amd.synth", fromlist=["x"]).grid_system(
+                       side, side, side, 5, "14rand", 0.10, seed=2),
+                   side=40, sample_side=40, tau=0.8, levels=3, droptol=1e-4, restart=50),
+}
 
 
-def _cpu_baseline(system):
-    """The oracle, single-threaded, on the same system: compress + factor + FGMRES."""
-    import numpy as np
+def _host_cpu():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 0
+
+
+def _cpu_baseline(wl, n_full):
+    """The oracle, single-threaded, on a smaller grid of the same recipe: compress +
+    factor + FGMRES; the time is scaled to the full workload by the ratio of unknowns."""
     from oracle import oracle as O
 
+    system = wl["make"](wl["sample_side"])
     t0 = time.perf_counter()
-    po, bo = O.compress(system.n, system.rowptr, system.col, TAU)
-    orc = O.Oracle(system.n, system.rowptr, system.col, system.val, po, bo, LEVELS, DROPTOL)
-    x, st, its, rel, _ = O.fgmres(system.n, system.rowptr, system.col, system.val, system.b, orc, TOL, RESTART,
-                                  MAXIT)
+    po, bo = O.compress(system.n, system.rowptr, system.col, wl["tau"])
+    orc = O.Oracle(system.n, system.rowptr, system.col, system.val, po, bo, wl["levels"], wl["droptol"])
+    x, st, its, rel, _ = O.fgmres(system.n, system.rowptr, system.col, system.val, system.b, orc, TOL,
+                                  wl["restart"], MAXIT)
     dt = time.perf_counter() - t0
-    return {"value": round(dt, 3), "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"the full workload once (one compress + factor + FGMRES solve; status {st}, "
-                      f"{its} iterations, true rel. residual {rel:.2e})"}
+    model, ncpu = _host_cpu()
+    side = wl["sample_side"]
+    return {"value": round(dt * n_full / system.n, 3), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"the same recipe on a {side}^3 grid (n={system.n}): one compress + factor + FGMRES solve "
+                      f"took {dt:.2f} s (status {st}, {its} iterations, true rel. residual {rel:.2e}); value "
+                      f"scales it by n_full/n_sample = {n_full / system.n:.3f}",
+            "host_cpu": model, "host_logical_cpus": ncpu}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=("f64", "f32"), default="f64")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="upwind74")
+    ap.add_argument("--precisions", default="f64,f32", help="comma list of f64 / f32 (the last one is `value`)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (the reference for counter scaling)")
@@ -64,10 +99,9 @@ def main() -> int:
               "multi-GPU path (--gpus must be 1)", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
-    from paper_1508_02219_amd import synth, vbarms as V
+    from paper_1508_02219_amd import vbarms as V
 
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
@@ -82,62 +116,102 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}), flush=True)
         return 0
-    system = synth.config_system(2)
+    wl = WORKLOADS[args.workload]
+    tau, levels, droptol, restart = wl["tau"], wl["levels"], wl["droptol"], wl["restart"]
+    system = wl["make"](wl["side"])
     print(f"[bench] workload {system.name} n={system.n} nnz={system.nnz}", file=sys.stderr, flush=True)
     rp, ci, va = V.csr_to_device(system)
     b = torch.as_tensor(system.b, device="cuda")
-    prec = V.F32 if args.precision == "f32" else V.F64
     sv = V.Solver()
+    precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
 
-    def step():
-        _, _, st = sv.compress(rp, ci, va, TAU)
-        sv.factor(LEVELS, DROPTOL, 1, prec)
-        x, info = sv.solve(b, tol=TOL, restart=RESTART, maxit=MAXIT)
+    def step(prec):
+        _, _, st = sv.compress(rp, ci, va, tau)
+        sv.factor(levels, droptol, 1, V.F32 if prec == "f32" else V.F64)
+        x, info = sv.solve(b, tol=TOL, restart=restart, maxit=MAXIT)
         return st, info
 
-    for w in range(args.warmup):
-        print(f"[bench] warmup {w + 1}/{args.warmup}", file=sys.stderr, flush=True)
-        step()
-    sv.set_timing(True)
-    torch.cuda.synchronize()
-    phases = {"compress_ms": 0.0, "factor_ms": 0.0, "solve_ms": 0.0}
-    iters = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        st, info = step()
-        if info.status != 0 or info.true_relres > TOL:
-            print(f"[bench] step {k + 1} did not converge: status {info.status} relres {info.true_relres:.3e}",
-                  file=sys.stderr, flush=True)
-            return 1
+    runs = {}
+    for prec in precs:
+        for w in range(args.warmup):
+            print(f"[bench] {prec} warmup {w + 1}/{args.warmup}", file=sys.stderr, flush=True)
+            step(prec)
+        phases = {"compress_ms": [], "factor_ms": [], "solve_ms": [], "ilut_ms": []}
+        iters, relres = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            st, info = step(prec)
+            if info.status != 0 or info.true_relres > TOL:
+                print(f"[bench] {prec} step {k + 1} did not converge: status {info.status} "
+                      f"relres {info.true_relres:.3e}", file=sys.stderr, flush=True)
+                return 1
+            fs = sv.stats()
+            for key in phases:
+                phases[key].append(getattr(fs, key))
+            iters.append(info.iters)
+            relres.append(info.true_relres)
+            print(f"[bench] {prec} step {k + 1}/{args.steps}: its {info.iters} relres {info.true_relres:.2e} "
+                  f"compress {fs.compress_ms:.1f} factor {fs.factor_ms:.1f} (ilut {fs.ilut_ms:.1f}, "
+                  f"{fs.ilut_waves} waves) solve {fs.solve_ms:.1f} ms", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
         fs = sv.stats()
-        for key in phases:
-            phases[key] += getattr(fs, key)
-        iters.append(info.iters)
-        print(f"[bench] step {k + 1}/{args.steps}: its {info.iters} relres {info.true_relres:.2e} "
-              f"compress {fs.compress_ms:.1f} factor {fs.factor_ms:.1f} solve {fs.solve_ms:.1f} ms",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kst = sv.kernel_stats()
-    sv.set_timing(False)
-    fs = sv.stats()
-    ms_per_step = 1000.0 * elapsed / args.steps
+        # measurement pass (untimed): HIP events around every launch class
+        sv.set_timing(True)
+        step(prec)
+        kst = sv.kernel_stats()
+        sv.set_timing(False)
+        fsm = sv.stats()
+        runs[prec] = dict(s=elapsed / args.steps, phases=phases, iters=iters, relres=relres, st=st, fs=fs, kst=kst,
+                          fsm=fsm)
 
-    # dominant launch class by time; its algorithmic bytes per call over its mean call time
+    mem = V.device_memory()
+    sv.close()
+    head = precs[-1]
+    R = runs[head]
+    ms_per_step = 1000.0 * R["s"]
+
+    def per_class(kst):
+        return {k: {"calls": v[0], "ms": round(v[1], 3), "avg_us": round(1000.0 * v[1] / v[0], 3) if v[0] else None,
+                    "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 2) if v[1] > 0 and v[2] > 0 else None}
+                for k, v in kst.items()}
+
+    # Roofline of the dominant launch class (by event time in the measurement pass).  For
+    # the block ILUT, the algorithmic bytes are those of its result: read the matrix handed
+    # to it, write L, U and the pivot-block LU factors (exported sizes), divided over its
+    # launches; the other classes count the bytes their launches must move (see the
+    # library's kernel table).
+    kst, fsm = R["kst"], R["fsm"]
     timed = {k: v for k, v in kst.items() if v[0] > 0}
     dom = max(timed, key=lambda k: timed[k][1])
     calls, ms, nbytes = timed[dom]
+    if dom == "ilut_wave":
+        nbytes = calls * (fsm.ilut_result_bytes / max(calls, 1))
     achieved = (nbytes / calls) / (ms / calls * 1e-3) / 1e9 if nbytes > 0 else None
     roofline = {"bound": "hbm", "kernel": dom, "calls": calls, "avg_us": round(1000.0 * ms / calls, 3),
-                "achieved": None if achieved is None else round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": None if achieved is None else round(achieved / HBM_PEAK_GBPS, 4), "traffic": None}
-    per_class = {k: {"calls": v[0], "ms": round(v[1], 3),
-                     "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 2) if v[1] > 0 and v[2] > 0 else None}
-                 for k, v in kst.items()}
+                "bytes_per_launch": round(nbytes / calls), "achieved": None if achieved is None else round(achieved, 3),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": None if achieved is None else round(achieved / HBM_PEAK_GBPS, 6), "traffic": None}
+
+    def summary(prec):
+        r = runs[prec]
+        pc = per_class(r["kst"])
+        f = r["fs"]
+        mean = {k: round(sum(v) / len(v), 2) for k, v in r["phases"].items()}
+        return {"s_per_solve": round(r["s"], 4), "phases_ms_mean": mean,
+                "phases_ms_spread": {k: round(max(v) - min(v), 2) for k, v in r["phases"].items()},
+                "iters": r["iters"], "max_true_relres": max(r["relres"]),
+                "levels_factored": f.levels, "last_level_supernodes": f.last_p, "ilut_waves": f.ilut_waves,
+                "ilut_attempts": f.ilut_attempts, "mem_ratio": round(f.factor_values / max(f.nnz, 1), 3),
+                "factor_breakdown_ms": {"levels": [round(f.factor_level_ms[l], 2) for l in range(f.levels)],
+                                        "last_level_ilut": round(f.ilut_ms, 2)},
+                "spmv_GBps": pc["spmv"]["GBps"], "apply_GBps": pc["apply"]["GBps"],
+                "trsv_GBps": pc["trsv_sweeps"]["GBps"], "kernels": pc}
 
     out = {
         "metric": METRIC,
-        "value": round(ms_per_step / 1000.0, 4),
+        "value": round(R["s"], 4),
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -146,29 +220,21 @@ def main() -> int:
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == V.F64 else "f32 factors, f64 krylov",
+        "dtype": "f32 factors + f64 fgmres" if head == "f32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "grid40^3 14-neighbour random stencil, 5 unknowns/node, 10% block perturbation",
-                   "n": system.n, "nnz": system.nnz, "tau": TAU, "levels": LEVELS, "droptol": DROPTOL,
-                   "krylov": f"FGMRES({RESTART})", "tol": TOL, "rhs": "A*1"},
-        "phases_ms_mean": {k: round(v / args.steps, 2) for k, v in phases.items()},
-        "iters": iters,
-        "blocks": st.nblocks,
-        "levels_factored": fs.levels,
-        "last_level_supernodes": fs.last_p,
-        "mem_ratio": round(fs.factor_values / max(fs.nnz, 1), 3),
-        "factor_breakdown_ms": {"levels": [round(fs.factor_level_ms[l], 2) for l in range(fs.levels)],
-                                "last_level_ilut": round(fs.ilut_ms, 2)},
-        "spmv_lanes": fs.spmv_lanes,
-        "spmv_GBps": per_class["spmv"]["GBps"],
-        "apply_GBps": per_class["apply"]["GBps"],
-        "kernels": per_class,
+        "config": {"workload": wl["desc"], "n": system.n, "nnz": system.nnz, "blocks": R["st"].nblocks,
+                   "tau": tau, "levels": levels, "droptol": droptol, "krylov": f"FGMRES({restart})", "tol": TOL,
+                   "rhs": "A*1"},
+        "runs": {p: summary(p) for p in precs},
+        "device_memory_GiB": {"peak_live": round(mem["peak"] / 2**30, 2), "cached": round(mem["cached"] / 2**30, 2),
+                              "runtime_allocs": mem["runtime_allocs"]},
         "roofline": roofline,
     }
-    sv.close()
+    if "f64" in runs and "f32" in runs:
+        out["mixed_speedup_vs_fp64"] = round(runs["f64"]["s"] / runs["f32"]["s"], 4)
     if not args.no_cpu_baseline:
         print("[bench] oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = _cpu_baseline(system)
+        out["cpu_baseline"] = _cpu_baseline(wl, system.n)
     print(json.dumps(out), flush=True)
     return 0
 

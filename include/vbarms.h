@@ -81,14 +81,21 @@ typedef struct {
     double av_bs;
 } vbarms_cstats;
 
+/* visiting order of the greedy block independent set (Sec. 3, Step 3) */
+#define VBARMS_IS_NATURAL 0   /* supernodes in ascending order (Sec. 2, the simple greedy) */
+#define VBARMS_IS_WEIGHTED 1  /* descending ||A_II||_F / sum_J ||A_IJ||_F of the scaled level
+                                 matrix, ties ascending (Sec. 3, "weighted greedy") */
+
 /* Factorization parameters.  droptol[l] is the threshold t of level l (Sec. 3: a block B
  * of size m x n is dropped when ||B||_F / (m n) < t); droptol[levels] is used by the
  * last-level block ILUT.  drop_schur = 1 also drops small off-diagonal blocks of every
- * Schur complement; 0 keeps them all (the paper's wording for intermediate levels). */
+ * Schur complement; 0 keeps them all (the paper's wording for intermediate levels).
+ * Zero-initialize the struct: 0 selects the default of every field. */
 typedef struct {
     int32_t levels;                        /* number of Schur reductions (0 = block ILUT only) */
     double droptol[VBARMS_MAX_LEVELS + 1];
     int32_t drop_schur;
+    int32_t is_order;                      /* VBARMS_IS_NATURAL or VBARMS_IS_WEIGHTED */
     int32_t precision;                     /* VBARMS_F64 or VBARMS_F32 */
 } vbarms_fparams;
 
@@ -97,6 +104,8 @@ typedef struct {
     int32_t restarts;    /* completed restart cycles */
     double true_relres;  /* ||b - A x|| / ||b|| of the returned x */
     int32_t status;      /* same as the return value */
+    int32_t fp64_refactor; /* 1 when FP32 factors did not converge within the FP32 step limit and
+                              the solve recomputed them in FP64 (see vbarms_set_fp64_fallback) */
 } vbarms_sinfo;
 
 /* Phase timings of the last calls, milliseconds of device time on the handle's stream. */
@@ -110,6 +119,16 @@ typedef struct {
     int64_t nnz;             /* nnz(A) */
     int32_t spmv_lanes;      /* lanes per scalar row of the FGMRES product, picked at compression by
                                 timing 4, 8, 16 and 32 on the compressed matrix */
+    int32_t ilut_waves;      /* dependency-wave launches of the last-level block ILUT */
+    int32_t ilut_attempts;   /* runs of the block ILUT: more than 1 when its working room ran out
+                                and it started again with more (the handle keeps the larger room) */
+    double ilut_result_bytes;/* algorithmic bytes of the block ILUT: its input matrix read once and
+                                L, U, the pivot-block LU factors and pivots written once */
+    int32_t illcond_blocks;  /* pivot blocks of the last factorization whose pivot ratio (smallest over
+                                largest pivot magnitude) fell below the fallback threshold */
+    int32_t fp64_fallback;   /* 0: factors in the requested precision; 1: FP32 was requested but an
+                                ill-conditioned pivot block sent the factorization to FP64; 2: a
+                                solve with FP32 factors stagnated and refactored in FP64 */
 } vbarms_fstats;
 
 /* Creates a handle bound to the current HIP device and to `hip_stream` (a hipStream_t,
@@ -160,8 +179,28 @@ int vbarms_spmv(vbarms_t h, const double *x, double *y);
 int vbarms_solve(vbarms_t h, const double *b, double *x, double tol, int32_t restart,
                  int32_t maxit, vbarms_sinfo *info);
 
+/* Safeguards of FP32 factors (mixed precision; FGMRES is FP64 throughout).  With enable != 0
+ * (the default):
+ *  - a factorization requested in FP32 is redone in FP64 when any pivot block (the
+ *    independent-set blocks of every level and the last level's diagonal blocks) has a
+ *    pivot ratio min|u_kk| / max|u_kk| below min_pivot_ratio (default 1e-4: at FP32
+ *    rounding such a block loses about four more digits than a well-conditioned one);
+ *  - a solve with FP32 factors that has not converged after f32_iter_limit Arnoldi steps
+ *    (default 100) recomputes the factors in FP64 with the same parameters and continues
+ *    FGMRES from its current iterate; vbarms_sinfo.fp64_refactor reports it.
+ * The handle's factors stay FP64 afterwards.  Errors: ARG (negative limit, ratio outside
+ * [0, 1]). */
+int vbarms_set_fp64_fallback(vbarms_t h, int32_t enable, int32_t f32_iter_limit, double min_pivot_ratio);
+
 /* Timings and sizes of the last compress / factor / solve on this handle (HOST). */
 int vbarms_get_stats(vbarms_t h, vbarms_fstats *st);
+
+/* Device memory of the library in this process (HOST out[4]): bytes in use, bytes kept in
+ * the library's cache for reuse, the peak of bytes in use, and the number of allocations
+ * that reached the HIP runtime.  Freed buffers are cached per stream and reused for later
+ * work on the same stream, so repeated factorizations of one matrix stop allocating after
+ * the first.  Never fails. */
+int vbarms_device_memory(int64_t *out);
 
 /* enable != 0 (the default) replays the level launches of the last-level triangular
  * sweeps from a HIP graph captured at the first application after each factorization;

@@ -27,7 +27,14 @@ struct vbarms_ctx {
     DBuf<double> wx, wy;        // permuted in/out vectors
     KrylovWork kw;
     KTimer kt;                  // optional kernel timing
+    IlutHint ilut_hint;         // room the last-level ILUT needed so far
     bool graphs = true;         // replay the last-level sweeps from a captured graph
+    vbarms_fparams params{};    // parameters of the last factorization
+    // FP32 safeguards: redo in FP64 when a pivot block's pivot ratio is below min_pivot_ratio
+    // (at factorization) or when FGMRES has not converged after f32_iter_limit steps
+    bool fb_enable = true;
+    int fb_iter_limit = 100;
+    double fb_min_ratio = 1e-4;
 };
 
 namespace {
@@ -85,11 +92,12 @@ int guarded(vbarms_t h, F &&body) {
     }
 }
 
-// converts a device error record into an exception
-void check_dev_err(vbarms_t h, const char *stage) {
+// converts a device error record into an exception; returns the record's count of
+// ill-conditioned pivot blocks
+int check_dev_err(vbarms_t h, const char *stage) {
     std::vector<int> rec;
     to_host(rec, h->err.rec.p, 4, h->stream);
-    if (rec[0] == 0) return;
+    if (rec[0] == 0) return rec[3];
     h->err_level = rec[1];
     h->err_block = rec[2];
     std::string msg = std::string(stage) + ": ";
@@ -102,6 +110,7 @@ void check_dev_err(vbarms_t h, const char *stage) {
     default: msg += "inconsistent factor data (level " + std::to_string(rec[1]) + ", row " + std::to_string(rec[2]) + ")"; break;
     }
     fail(rec[0], msg);
+    return rec[3];
 }
 
 void validate_csr(const vbarms_csr *A) {
@@ -134,13 +143,16 @@ void finish_partition(vbarms_t h, const vbarms_csr *A, vbarms_cstats *st) {
     h->wy.alloc(std::max(A->n, 1));
 }
 
+// Factors the compressed matrix in precision T; returns the number of pivot blocks whose
+// pivot ratio fell below the handle's threshold.
 template <class T>
-void factor_impl(vbarms_t h, const vbarms_fparams *p, std::unique_ptr<Factors<T>> &fp) {
+int factor_impl(vbarms_t h, const vbarms_fparams *p, std::unique_ptr<Factors<T>> &fp) {
     hipStream_t s = h->stream;
     fp.reset(new Factors<T>());
     Factors<T> &f = *fp;
     const int levels = p->levels;
     f.lev.reserve(levels + 1);
+    int ill_levels = 0;
     Panel<T> cur;
     panel_convert<double, T>(h->A, cur, s);
     h->err.reset(s);
@@ -149,9 +161,10 @@ void factor_impl(vbarms_t h, const vbarms_fparams *p, std::unique_ptr<Factors<T>
         Timer tm(s);
         f.lev.emplace_back();
         Panel<T> next;
-        factor_level<T>(f.lev[l], std::move(cur), l, p->droptol[l], p->drop_schur, next, h->err.rec.p, s);
+        factor_level<T>(f.lev[l], std::move(cur), l, p->droptol[l], p->drop_schur, p->is_order, h->fb_min_ratio,
+                        next, h->err.rec.p, s);
         f.nlev = l + 1;
-        check_dev_err(h, "factor");
+        ill_levels = check_dev_err(h, "factor");
         f.level_ms[l] = tm.stop();
         cur = std::move(next);
         if (f.lev[l].nis == 0) break;
@@ -159,13 +172,15 @@ void factor_impl(vbarms_t h, const vbarms_fparams *p, std::unique_ptr<Factors<T>
     f.last.A = std::move(cur);
     f.last.use_graph = h->graphs;
     Timer tm(s);
-    factor_last<T>(f.last, p->droptol[levels], f.nlev, h->err.rec.p, s);
-    check_dev_err(h, "last-level ILUT");
+    factor_last<T>(f.last, p->droptol[levels], h->fb_min_ratio, f.nlev, h->ilut_hint, h->err.rec.p, s);
+    const int ill = ill_levels + check_dev_err(h, "last-level ILUT");
     f.ilut_ms = tm.stop();
     h->stats.levels = f.nlev;
     h->stats.last_p = f.last.A.p;
     for (int l = 0; l < VBARMS_MAX_LEVELS; ++l) h->stats.factor_level_ms[l] = l < f.nlev ? f.level_ms[l] : 0.0;
     h->stats.ilut_ms = f.ilut_ms;
+    h->stats.ilut_waves = f.last.waves;
+    h->stats.ilut_attempts = f.last.attempts;
     int64_t vals = 0;
     // bytes of one application: per level the pivot-block factors, G, W and their column
     // lists, the pivots and about six passes over the level's vectors; then both sweeps
@@ -183,8 +198,24 @@ void factor_impl(vbarms_t h, const vbarms_fparams *p, std::unique_ptr<Factors<T>
         std::vector<int64_t> d;
         to_host(d, f.last.dl_off.p + f.last.A.p, 1, s);
         vals += d[0] + f.last.L.nv + f.last.U.nv;
+        const LastLevel<T> &ll = f.last;
+        const int64_t nlast = ll.A.h_rb.empty() ? 0 : ll.A.h_rb.back();
+        h->stats.ilut_result_bytes = (double)sizeof(T) * (double)(ll.A.nv + ll.L.nv + ll.U.nv + d[0]) +
+                                     4.0 * (double)(ll.A.nb + ll.L.nb + ll.U.nb) + 4.0 * (double)nlast;
     }
     h->stats.factor_values = vals;
+    return ill;
+}
+
+// Replaces FP32 factors by FP64 factors of the same matrix and parameters.
+void refactor_fp64(vbarms_t h) {
+    vbarms_fparams q = h->params;
+    q.precision = VBARMS_F64;
+    h->have_factors = false;
+    h->f32.reset();
+    h->precision = VBARMS_F64;
+    h->stats.illcond_blocks = factor_impl<double>(h, &q, h->f64);
+    h->have_factors = true;
 }
 
 // M^{-1} in the compressed numbering
@@ -291,14 +322,6 @@ int vbarms_create(vbarms_t *out, void *hip_stream) {
     if (!h) return VBARMS_ERR_OOM;
     if (hipGetDevice(&h->device) != hipSuccess) { delete h; return VBARMS_ERR_HIP; }
     h->stream = (hipStream_t)hip_stream;
-    {
-        // keep freed stream-ordered memory in the device pool instead of returning it at every sync
-        hipMemPool_t pool = nullptr;
-        if (hipDeviceGetDefaultMemPool(&pool, h->device) == hipSuccess && pool) {
-            uint64_t keep = UINT64_MAX;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-        }
-    }
     int rc = guarded(h, [&] {
         h->err.reset(h->stream);
         return VBARMS_OK;
@@ -368,15 +391,37 @@ int vbarms_factor(vbarms_t h, const vbarms_fparams *p) {
         for (int l = 0; l <= p->levels; ++l)
             if (!(p->droptol[l] >= 0.0) || !std::isfinite(p->droptol[l])) fail(VBARMS_ERR_ARG, "invalid drop tolerance");
         if (p->precision != VBARMS_F64 && p->precision != VBARMS_F32) fail(VBARMS_ERR_ARG, "invalid precision");
+        if (p->is_order != VBARMS_IS_NATURAL && p->is_order != VBARMS_IS_WEIGHTED)
+            fail(VBARMS_ERR_ARG, "invalid independent-set order");
         if (!h->have_A) fail(VBARMS_ERR_STATE, "no compressed matrix: call vbarms_compress first");
         h->have_factors = false;
         h->err_level = h->err_block = -1;
         h->f64.reset();
         h->f32.reset();
         h->precision = p->precision;
+        h->params = *p;
+        h->stats.fp64_fallback = 0;
         Timer tm(h->stream);
-        if (p->precision == VBARMS_F32) factor_impl<float>(h, p, h->f32);
-        else factor_impl<double>(h, p, h->f64);
+        if (p->precision == VBARMS_F32) {
+            bool redo = false;
+            try {
+                h->stats.illcond_blocks = factor_impl<float>(h, p, h->f32);
+                redo = h->fb_enable && h->stats.illcond_blocks > 0;
+            } catch (const VbError &e) {
+                // a pivot block that is singular in FP32 may not be in FP64
+                if (!h->fb_enable || e.code != VBARMS_ERR_SINGULAR) throw;
+                h->stats.illcond_blocks = 1;
+                redo = true;
+            }
+            if (redo) {
+                // an FP32 pivot block is ill-conditioned: the whole factorization runs in FP64
+                h->err_level = h->err_block = -1;
+                refactor_fp64(h);
+                h->stats.fp64_fallback = 1;
+            }
+        } else {
+            h->stats.illcond_blocks = factor_impl<double>(h, p, h->f64);
+        }
         h->stats.factor_ms = tm.stop();
         h->have_factors = true;
         return VBARMS_OK;
@@ -429,12 +474,53 @@ int vbarms_solve(vbarms_t h, const double *b, double *x, double tol, int32_t res
         gather_perm(h->n, h->perm.p, b, bc.p, s);
         gather_perm(h->n, h->perm.p, x, xc.p, s);
         auto pre = [&](const double *in, double *out) { precond_apply(h, in, out); };
-        int st = fgmres_run(h->A, h->kw, bc.p, xc.p, tol, restart, maxit, pre, info, s);
+        vbarms_sinfo i1{}, i2{};
+        int st;
+        if (h->precision == VBARMS_F32 && h->fb_enable && h->fb_iter_limit < maxit) {
+            // FP32 factors get fb_iter_limit Arnoldi steps; if FGMRES has not converged by
+            // then, the factors are recomputed in FP64 and FGMRES continues from its iterate
+            st = fgmres_run(h->A, h->kw, bc.p, xc.p, tol, restart, h->fb_iter_limit, pre, &i1, s);
+            check_dev_err(h, "solve");
+            if (st == VBARMS_NOT_CONVERGED) {
+                refactor_fp64(h);
+                h->stats.fp64_fallback = 2;
+                h->err.reset(s);
+                st = fgmres_run(h->A, h->kw, bc.p, xc.p, tol, restart, maxit - i1.iters, pre, &i2, s);
+                i2.iters += i1.iters;
+                i2.restarts += i1.restarts;
+                i2.fp64_refactor = 1;
+                i1 = i2;
+            }
+        } else {
+            st = fgmres_run(h->A, h->kw, bc.p, xc.p, tol, restart, maxit, pre, &i1, s);
+        }
+        if (info) *info = i1;
         check_dev_err(h, "solve");
         scatter_perm(h->n, h->perm.p, xc.p, x, s);
         VB_HIP(hipStreamSynchronize(s));
         h->stats.solve_ms = tm.stop();
         return st;
+    });
+}
+
+int vbarms_device_memory(int64_t *out) {
+    if (!out) return VBARMS_ERR_ARG;
+    const DevCacheStats c = dev_cache_stats();
+    out[0] = (int64_t)c.live_bytes;
+    out[1] = (int64_t)c.cached_bytes;
+    out[2] = (int64_t)c.peak_bytes;
+    out[3] = c.runtime_allocs;
+    return VBARMS_OK;
+}
+
+int vbarms_set_fp64_fallback(vbarms_t h, int32_t enable, int32_t f32_iter_limit, double min_pivot_ratio) {
+    return guarded(h, [&] {
+        if (f32_iter_limit < 0 || !(min_pivot_ratio >= 0.0) || !(min_pivot_ratio <= 1.0))
+            fail(VBARMS_ERR_ARG, "invalid fallback settings");
+        h->fb_enable = enable != 0;
+        h->fb_iter_limit = f32_iter_limit;
+        h->fb_min_ratio = min_pivot_ratio;
+        return VBARMS_OK;
     });
 }
 

@@ -128,6 +128,19 @@ struct KScope {
     KScope &operator=(const KScope &) = delete;
 };
 
+// Device memory comes from a caching allocator kept per stream (util.hip).  A block
+// released on stream s goes back to that stream's free list and is handed out again only
+// to work enqueued later on s, so stream order alone makes the reuse safe; no block is
+// returned to the runtime while the process runs (except to retry a failed allocation),
+// so a steady stream of factorizations of one matrix allocates nothing after the first.
+void *dev_alloc(size_t bytes, hipStream_t s);  // throws VbError(OOM)
+void dev_free(void *p, hipStream_t s);
+struct DevCacheStats {
+    size_t live_bytes, cached_bytes, peak_bytes;
+    int64_t runtime_allocs;  // calls that reached hipMalloc
+};
+DevCacheStats dev_cache_stats();
+
 template <class T>
 struct DBuf {
     T *p = nullptr;
@@ -146,11 +159,12 @@ struct DBuf {
         release();
         n = count;
         if (count) {
-            hipError_t e = hipMallocAsync((void **)&p, count * sizeof(T), cur_stream());
-            if (e != hipSuccess) {
+            try {
+                p = (T *)dev_alloc(count * sizeof(T), cur_stream());
+            } catch (...) {
                 p = nullptr;
                 n = 0;
-                fail(VBARMS_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+                throw;
             }
         }
     }
@@ -159,7 +173,7 @@ struct DBuf {
         if (count > n) alloc(count);
     }
     void release() {
-        if (p) (void)hipFreeAsync(p, cur_stream());
+        if (p) dev_free(p, cur_stream());
         p = nullptr;
         n = 0;
     }
@@ -295,6 +309,24 @@ __device__ inline bool dev_gepp(int m, T *a, int *piv) {
     }
     return true;
 }
+// Smallest over largest pivot magnitude of a factored m x m block: a cheap stand-in for
+// the reciprocal of its condition number (1 for a perfectly balanced block).
+template <class T>
+__device__ inline double dev_pivot_ratio(int m, const T *lu) {
+    double mn = 0.0, mx = 0.0;
+    for (int k = 0; k < m; ++k) {
+        const double a = fabs((double)lu[k * m + k]);
+        mn = k == 0 || a < mn ? a : mn;
+        mx = a > mx ? a : mx;
+    }
+    return mx > 0.0 ? mn / mx : 0.0;
+}
+// Counts a factored pivot block whose pivot ratio is below `min_ratio` in err[3].
+template <class T>
+__device__ inline void dev_count_illcond(int m, const T *lu, double min_ratio, int *err) {
+    if (min_ratio > 0.0 && dev_pivot_ratio<T>(m, lu) < min_ratio) atomicAdd(&err[3], 1);
+}
+
 // x <- L^{-1} P x
 template <class T, class V>
 __device__ inline void dev_lu_fwd(int m, const T *lu, const int *piv, V *x) {

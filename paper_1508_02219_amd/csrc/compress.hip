@@ -214,15 +214,23 @@ __global__ void __launch_bounds__(kSimThreads) k_sim_global(int nbig, const int 
 // lower neighbours are out, leaves when one of them is in.  `eptr/elist` hold lower
 // neighbours only; `elist2` (optional) a second lower-neighbour list.  Monotone, so races
 // between rounds only speed convergence.
+// true when u comes before v in the visiting order: ascending index, or with weights,
+// descending weight and ascending index among equal weights
+__device__ inline bool visits_before(int u, int v, const double *prio) {
+    if (!prio) return u < v;
+    const double wu = prio[u], wv = prio[v];
+    return wu > wv || (wu == wv && u < v);
+}
+
 __global__ void k_lfmis_round(int nv, const int64_t *eptr, const int *elist, const int64_t *eptr2,
-                              const int *elist2, int *state, int *undecided) {
+                              const int *elist2, const double *prio, int *state, int *undecided) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nv) return;
     if (__atomic_load_n(&state[v], __ATOMIC_RELAXED) != 0) return;
     bool any_in = false, all_out = true;
     for (int64_t e = eptr[v]; e < eptr[v + 1]; ++e) {
         int u = elist[e];
-        if (u >= v) continue;
+        if (u == v || !visits_before(u, v, prio)) continue;
         int s = __atomic_load_n(&state[u], __ATOMIC_RELAXED);
         if (s == 1) { any_in = true; break; }
         if (s != 2) all_out = false;
@@ -230,7 +238,7 @@ __global__ void k_lfmis_round(int nv, const int64_t *eptr, const int *elist, con
     if (!any_in && elist2) {
         for (int64_t e = eptr2[v]; e < eptr2[v + 1]; ++e) {
             int u = elist2[e];
-            if (u >= v) continue;
+            if (u == v || !visits_before(u, v, prio)) continue;
             int s = __atomic_load_n(&state[u], __ATOMIC_RELAXED);
             if (s == 1) { any_in = true; break; }
             if (s != 2) all_out = false;
@@ -283,8 +291,8 @@ __global__ void k_group_sort(int p, const int *bptr, int *perm) {
 }  // namespace
 
 // Lexicographically first MIS by rounds; shared with the independent-set step.
-void lfmis(int nv, const int64_t *eptr, const int *elist, const int64_t *eptr2, const int *elist2, int *state,
-           hipStream_t s) {
+void lfmis(int nv, const int64_t *eptr, const int *elist, const int64_t *eptr2, const int *elist2, const double *prio,
+           int *state, hipStream_t s) {
     fill_i32(state, 0, nv, s);
     if (nv == 0) return;
     DBuf<int> und(1);
@@ -293,7 +301,7 @@ void lfmis(int nv, const int64_t *eptr, const int *elist, const int64_t *eptr2, 
         for (int b = 0; b < batch; ++b) {
             bool last = b == batch - 1;
             if (last) VB_HIP(hipMemsetAsync(und.p, 0, sizeof(int), s));
-            k_lfmis_round<<<grid_for(nv, 256), 256, 0, s>>>(nv, eptr, elist, eptr2, elist2, state,
+            k_lfmis_round<<<grid_for(nv, 256), 256, 0, s>>>(nv, eptr, elist, eptr2, elist2, prio, state,
                                                              last ? und.p : nullptr);
             VB_LAUNCH_CHECK();
         }
@@ -391,7 +399,7 @@ void similarity_groups(int n, const int64_t *rowptr, const int *col, const int *
         VB_LAUNCH_CHECK();
     }
     DBuf<int> state(std::max(nr, 1)), seedrep(std::max(nr, 1));
-    lfmis(nr, eptr.p, elist.p, nullptr, nullptr, state.p, s);
+    lfmis(nr, eptr.p, elist.p, nullptr, nullptr, nullptr, state.p, s);
     k_assign_rep<<<grid_for(nr, 256), 256, 0, s>>>(nr, replist.p, eptr.p, elist.p, state.p, seedrep.p);
     VB_LAUNCH_CHECK();
     k_assign_row<<<grid_for(n, 256), 256, 0, s>>>(n, rep, repidx.p, seedrep.p, seed);

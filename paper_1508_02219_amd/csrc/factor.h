@@ -57,6 +57,7 @@ struct LastLevel {
     std::vector<int> uorder, uptr;  // backward sweep
     DBuf<int64_t> d_lrows, d_urows; // row descriptors of the two sweeps, in sweep order
     int waves = 0;                  // kernel launches the factorization took
+    int attempts = 0;               // runs of the factorization (more than one after a capacity retry)
     double sweep_bytes = 0;         // algorithmic bytes of one forward + backward sweep
     DBuf<double> t;               // solve workspace [n]
     // the two sweeps captured once as a graph that reads gb and writes gx
@@ -84,8 +85,11 @@ struct DevErr {
     }
 };
 
-void lfmis(int nv, const int64_t *eptr, const int *elist, const int64_t *eptr2, const int *elist2, int *state,
-           hipStream_t s);
+// Lexicographically first maximal independent set of a graph given by one or two
+// adjacency lists (state: 1 in the set, 2 out).  The visiting order is ascending vertex
+// number, or, when prio is given, descending prio with ties in ascending number.
+void lfmis(int nv, const int64_t *eptr, const int *elist, const int64_t *eptr2, const int *elist2, const double *prio,
+           int *state, hipStream_t s);
 std::vector<int> compress_gpu(int n, const int64_t *rowptr, const int *col, double tau, int *perm, hipStream_t s);
 void panel_from_csr(int n, const int64_t *rowptr, const int *col, const double *val, const int *perm,
                     const std::vector<int> &bptr, Panel<double> &out, int *err, hipStream_t s);
@@ -95,12 +99,22 @@ template <class Tin, class Tout>
 void panel_convert(const Panel<Tin> &src, Panel<Tout> &dst, hipStream_t s);
 
 // Factors level `lvl` of A (consumed), producing the next Schur complement in `next`.
+// Pivot blocks whose pivot ratio (smallest over largest pivot magnitude) falls below
+// min_ratio are counted in err[3].
 template <class T>
-void factor_level(Level<T> &L, Panel<T> &&A, int lvl, double droptol, int drop_schur, Panel<T> &next, int *err,
-                  hipStream_t s);
+void factor_level(Level<T> &L, Panel<T> &&A, int lvl, double droptol, int drop_schur, int is_order, double min_ratio,
+                  Panel<T> &next, int *err, hipStream_t s);
+// Room reserved by the block ILUT, kept by the caller across factorizations: working rows
+// hold `grow` times their input row; the L and U pools hold `pool` times the input's blocks
+// and values each.  Both only grow, when an attempt runs out of room.
+struct IlutHint {
+    int grow = 4;
+    double pool = 1.5;
+};
 // Block ILUT of `last.A` with threshold t.
 template <class T>
-void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStream_t s);
+void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, IlutHint &hint, int *err,
+                 hipStream_t s);
 // x = U^{-1} L^{-1} b for the last level (b and x may alias)
 template <class T>
 void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStream_t s);

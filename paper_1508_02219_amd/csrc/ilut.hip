@@ -21,13 +21,27 @@ namespace vb {
 
 namespace {
 
-constexpr int kIlutThreads = 256;
+// launch shape of the wave kernel (a build may override the defaults for tuning sweeps)
+#ifndef VB_ILUT_THREADS
+#define VB_ILUT_THREADS 256
+#endif
+#ifndef VB_ILUT_GRID
+#define VB_ILUT_GRID 1024
+#endif
+#ifndef VB_ILUT_USTAGE
+#define VB_ILUT_USTAGE 1024
+#endif
+#ifndef VB_ILUT_STEPCAP
+#define VB_ILUT_STEPCAP 8
+#endif
+constexpr int kIlutThreads = VB_ILUT_THREADS;
+static_assert(kIlutThreads % 64 == 0, "whole wavefronts");
 constexpr int kMaxRowBlocks = 1024;  // largest block list of one working row
-constexpr int kUStage = 1024;        // values of one LDS tile of U row k
+constexpr int kUStage = VB_ILUT_USTAGE;  // values of one LDS tile of U row k
 constexpr int kCheckEvery = 16;      // ILUT waves between host checks
-constexpr int kStepCap = 8;          // elimination steps a row takes per launch (the smallest
-                                     // ready row is exempt)
-constexpr int kIlutGrid = 1024;      // workgroups of every ILUT launch
+constexpr int kStepCap = VB_ILUT_STEPCAP;  // elimination steps a row takes per launch (the
+                                           // smallest ready row is exempt)
+constexpr int kIlutGrid = VB_ILUT_GRID;    // workgroups of every ILUT launch
 constexpr int kGatherBlocks = 256;   // workgroups of the gather kernel
 
 // sizes of the dynamic LDS of the ILUT wave kernel
@@ -184,8 +198,9 @@ template <class T>
 __device__ void ilut_row(
     const int i, int launch, int min_ready, int p, int *wait_out, int *cnt_wait_out, int *wait_on, int *nfinished,
     const int *rb, const int64_t *rp, const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av,
-    double droptol, int *done, RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols, int *woffs,
-    unsigned char *west, T *wvals, T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec, int *lci, int *lco,
+    double droptol, double min_ratio, int *done, RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols,
+    int *woffs, unsigned char *west, T *wvals, T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec, int *lci,
+    int *lco,
     T *lv, int *uci, int *uco, T *uv, int64_t *cursors, int64_t capb_pool, int64_t capv_pool, int *err, int lvl,
     unsigned long long *moved, IlutLds lds) {
     // dynamic LDS, carved as described by `lds` (sizes chosen on the host for this matrix)
@@ -536,6 +551,8 @@ __device__ void ilut_row(
         } else if (!dev_gepp<T>(m, s_M, s_piv)) {
             dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, i);
             for (int q = 0; q < m; ++q) s_piv[q] = q;
+        } else {
+            dev_count_illcond<T>(m, s_M, min_ratio, err);
         }
     }
     __syncthreads();
@@ -667,8 +684,9 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
     int launch, int p, const int *ready, const int *cnt_ready, int *cnt_ready_clear, const int *min_ready_in,
     int *min_ready_clear, int *wait_out,
     int *cnt_wait_out, int *cnt_wait_clear, int *wait_on, int *nfinished, const int *rb, const int64_t *rp,
-    const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av, double droptol, int *done,
-    RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols, int *woffs, unsigned char *west, T *wvals,
+    const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av, double droptol, double min_ratio,
+    int *done, RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols, int *woffs, unsigned char *west,
+    T *wvals,
     T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec, int *lci, int *lco, T *lv, int *uci, int *uco, T *uv,
     int64_t *cursors, int64_t capb_pool, int64_t capv_pool, int *err, int lvl, unsigned long long *moved,
     IlutLds lds) {
@@ -681,7 +699,8 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
     const int min_ready = *min_ready_in;
     for (int slot = blockIdx.x; slot < nin; slot += gridDim.x) {
         ilut_row<T>(ready[slot], launch, min_ready, p, wait_out, cnt_wait_out, wait_on, nfinished, rb, rp, ci, co, wp, vp, av,
-                    droptol, done, rs, boff, voff, wcols, woffs, west, wvals, dl, dl_off, dl_piv, rec, lci, lco, lv, uci,
+                    droptol, min_ratio, done, rs, boff, voff, wcols, woffs, west, wvals, dl, dl_off, dl_piv, rec, lci,
+                    lco, lv, uci,
                     uco, uv, cursors, capb_pool, capv_pool, err, lvl, moved, lds);
         __syncthreads();
     }
@@ -858,7 +877,8 @@ void level_schedule(int p, const std::vector<int64_t> &rp, const std::vector<int
 }  // namespace
 
 template <class T>
-void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStream_t s) {
+void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, IlutHint &hint, int *err,
+                 hipStream_t s) {
     Panel<T> &A = last.A;
     const int p = A.p;
     const int n = A.h_rb.empty() ? 0 : A.h_rb.back();
@@ -884,14 +904,16 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         last.U.rp.alloc(1); fill_i64(last.U.rp.p, 0, 1, s); panel_finish_layout(last.U, s);
         return;
     }
-    int grow = 8;
     int64_t max_na = 0;  // longest block row of the input
     {
         std::vector<int64_t> hrp;
         to_host(hrp, A.rp.p, p + 1, s);
         for (int i = 0; i < p; ++i) max_na = std::max(max_na, hrp[i + 1] - hrp[i]);
     }
-    for (int attempt = 0; attempt < 4; ++attempt) {
+    last.attempts = 0;
+    for (int attempt = 0; attempt < 10; ++attempt) {
+        ++last.attempts;
+        const int grow = hint.grow;
         // per-row working rows
         DBuf<int64_t> capb(p), capv(p), boff(p + 1), voff(p + 1);
         k_row_caps<<<grid_for(p, 256), 256, 0, s>>>(p, A.rb.p, A.rp.p, A.wp.p, grow, capb.p, capv.p);
@@ -903,9 +925,14 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
         DBuf<T> wvals(totv);
         DBuf<RowState> rs(p);
         DBuf<IlutRowRec> rec(p);
-        // a row's L and U output never exceed its working row, so pools as large as all
-        // working rows together cannot overflow
-        const int64_t capb_pool = std::max<int64_t>(totb, 1), capv_pool = std::max<int64_t>(totv, 1);
+        // the L and U pools are sized from the input matrix; a pool that runs out stops the
+        // attempt, which then runs again with larger pools.  A row's L and U output never
+        // exceed its working row, so pools as large as all working rows cannot run out:
+        // that bounds them.
+        const int64_t capb_pool = std::max<int64_t>(
+            std::min<int64_t>((int64_t)(hint.pool * (double)A.nb), totb), 64);
+        const int64_t capv_pool = std::max<int64_t>(
+            std::min<int64_t>((int64_t)(hint.pool * (double)A.nv), totv), (int64_t)64 * A.maxm);
         DBuf<int> lci(capb_pool), lco(capb_pool), uci(capb_pool), uco(capb_pool);
         DBuf<T> lv(capv_pool), uv(capv_pool);
         DBuf<int64_t> cursors(4);
@@ -952,7 +979,7 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
                     launch, p, ready.p, cr + launch % 2, cr + (launch + 1) % 2, mr + launch % 2, mr + (launch + 1) % 2,
                     w_out, cw + (launch + 1) % 3,
                     cw + (launch + 2) % 3, wait_on.p, nfin, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p,
-                    droptol, done.p, rs.p, boff.p, voff.p, wcols.p, woffs.p, west.p, wvals.p, last.dl.p,
+                    droptol, min_ratio, done.p, rs.p, boff.p, voff.p, wcols.p, woffs.p, west.p, wvals.p, last.dl.p,
                     last.dl_off.p, last.dl_piv.p, rec.p, lci.p, lco.p, lv.p, uci.p, uco.p, uv.p, cursors.p, capb_pool,
                     capv_pool, err, lvl, moved.p, lds);
                 VB_LAUNCH_CHECK();
@@ -975,10 +1002,11 @@ void factor_last(LastLevel<T> &last, double droptol, int lvl, int *err, hipStrea
             KTimer *kt = cur_ktimer();
             if (kt && kt->on) kt->tot[VBARMS_K_ILUT].bytes += (double)read_one(moved.p, s);
         }
-        if (code == VBARMS_ERR_OOM && attempt < 3) {
-            // a working row outgrew its capacity: start again with more room
-            (void)eblock;
-            grow *= 3;
+        if (code == VBARMS_ERR_OOM && attempt < 9) {
+            // a working row (eblock >= 0) or a pool (eblock < 0) ran out of room: start again
+            // with more, and keep the larger size for the next factorization on this handle
+            if (eblock >= 0) hint.grow *= 2;
+            else hint.pool *= 2.0;
             continue;
         }
         if (code != 0) return;  // reported by the caller from the error record
@@ -1092,8 +1120,8 @@ void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStr
     if (x != last.gx.p) VB_HIP(hipMemcpyAsync(x, last.gx.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
 }
 
-template void factor_last<double>(LastLevel<double> &, double, int, int *, hipStream_t);
-template void factor_last<float>(LastLevel<float> &, double, int, int *, hipStream_t);
+template void factor_last<double>(LastLevel<double> &, double, double, int, IlutHint &, int *, hipStream_t);
+template void factor_last<float>(LastLevel<float> &, double, double, int, IlutHint &, int *, hipStream_t);
 template void solve_last<double>(LastLevel<double> &, const double *, double *, int *, hipStream_t);
 template void solve_last<float>(LastLevel<float> &, const double *, double *, int *, hipStream_t);
 

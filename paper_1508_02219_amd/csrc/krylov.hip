@@ -207,6 +207,7 @@ int fgmres_run(const Panel<double> &A, KrylovWork &kw, const double *b, double *
         info->restarts = restarts;
         info->true_relres = rel;
         info->status = status;
+        info->fp64_refactor = 0;
     }
     return status;
 }

@@ -131,7 +131,7 @@ __global__ void k_block_sq(int nis, const int *is_list, const int *rb, int64_t *
 template <class T>
 __global__ void k_gepp(int nis, const int *is_list, const int *rb, const int64_t *rp, const int *ci, const int *co,
                        const int64_t *wp, const int64_t *vp, const T *v, const int64_t *dlu_off, const int *is_rb,
-                       T *dlu, int *dpiv, int lvl, int *err) {
+                       T *dlu, int *dpiv, double min_ratio, int lvl, int *err) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nis) return;
     int I = is_list[i];
@@ -144,6 +144,7 @@ __global__ void k_gepp(int nis, const int *is_list, const int *rb, const int64_t
     for (int r = 0; r < m; ++r)
         for (int c = 0; c < m; ++c) d[r * m + c] = a[r * W + c];
     if (!dev_gepp(m, d, dpiv + is_rb[i])) dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, I);
+    else dev_count_illcond<T>(m, d, min_ratio, err);
 }
 
 // G = L^{-1} P F: one lane per panel column of an independent block row (F columns only)
@@ -345,9 +346,38 @@ __global__ void k_keep_schur(int p, int64_t nb, const int64_t *rp, const int *ci
 
 }  // namespace
 
+// Weight of every block row for the weighted greedy independent set (Sec. 3, Step 3):
+// ||A_II||_F / sum_J ||A_IJ||_F, each block's squares summed row-major and the norms summed
+// in ascending block column; 0 for a row without stored blocks.
 template <class T>
-void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop_schur, Panel<T> &next, int *err,
-                  hipStream_t s) {
+__global__ void k_is_weights(int p, const int *rb, const int64_t *rp, const int *ci, const int *co,
+                             const int64_t *wp, const int64_t *vp, const T *v, double *w) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= p) return;
+    const int m = rb[I + 1] - rb[I];
+    const int64_t W = wp[I + 1] - wp[I];
+    const T *a = v + vp[I];
+    double diag = 0.0, tot = 0.0;
+    for (int64_t k = rp[I]; k < rp[I + 1]; ++k) {
+        const int J = ci[k];
+        const int c0 = co[k];
+        const int nJ = (k + 1 < rp[I + 1] ? co[k + 1] : (int)W) - c0;
+        double ss = 0.0;
+        for (int r = 0; r < m; ++r)
+            for (int c = 0; c < nJ; ++c) {
+                const double x = (double)a[(int64_t)r * W + c0 + c];
+                ss = ss + x * x;
+            }
+        const double f = sqrt(ss);
+        tot = tot + f;
+        if (J == I) diag = f;
+    }
+    w[I] = tot > 0.0 ? diag / tot : 0.0;
+}
+
+template <class T>
+void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop_schur, int is_order,
+                  double min_ratio, Panel<T> &next, int *err, hipStream_t s) {
     L.A = std::move(Ain);
     const Panel<T> &A = L.A;
     L.p = A.p;
@@ -375,8 +405,16 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
     }
     const Panel<T> &As = L.As;
 
-    // Step 3: independent set on the quotient graph of A + A^T, natural order
+    // Step 3: independent set on the quotient graph of A + A^T, in natural order or by
+    // descending weight
     DBuf<int> state(std::max(p, 1));
+    DBuf<double> wts;
+    if (is_order == 1 && p > 0) {
+        wts.alloc(p);
+        k_is_weights<T><<<grid_for(p, 256), 256, 0, s>>>(p, As.rb.p, As.rp.p, As.ci.p, As.co.p, As.wp.p, As.vp.p,
+                                                         As.v.p, wts.p);
+        VB_LAUNCH_CHECK();
+    }
     {
         DBuf<int> tcnt(std::max(p, 1)), tfill(std::max(p, 1));
         DBuf<int64_t> tptr(p + 1);
@@ -392,7 +430,7 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
             k_tfill<<<grid_for(p, 256), 256, 0, s>>>(p, As.rp.p, As.ci.p, tptr.p, tfill.p, tlist.p);
             VB_LAUNCH_CHECK();
         }
-        lfmis(p, As.rp.p, As.ci.p, tptr.p, tlist.p, state.p, s);
+        lfmis(p, As.rp.p, As.ci.p, tptr.p, tlist.p, wts.p, state.p, s);
     }
     // P_I: independent blocks ascending, then the rest ascending
     L.is_flag.alloc(std::max(p, 1));
@@ -439,7 +477,8 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
         L.dpiv.alloc(std::max(L.n_is, 1));
         if (nis > 0) {
             k_gepp<T><<<grid_for(nis, 64), 64, 0, s>>>(nis, L.is_list.p, As.rb.p, As.rp.p, As.ci.p, As.co.p, As.wp.p,
-                                                      As.vp.p, As.v.p, L.dlu_off.p, L.is_rb.p, L.dlu.p, L.dpiv.p, lvl,
+                                                      As.vp.p, As.v.p, L.dlu_off.p, L.is_rb.p, L.dlu.p, L.dpiv.p,
+                                                      min_ratio, lvl,
                                                       err);
             VB_LAUNCH_CHECK();
         }
@@ -515,9 +554,9 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
     L.t.alloc(std::max(L.n_is, 1));
 }
 
-template void factor_level<double>(Level<double> &, Panel<double> &&, int, double, int, Panel<double> &, int *,
-                                   hipStream_t);
-template void factor_level<float>(Level<float> &, Panel<float> &&, int, double, int, Panel<float> &, int *,
+template void factor_level<double>(Level<double> &, Panel<double> &&, int, double, int, int, double, Panel<double> &,
+                                   int *, hipStream_t);
+template void factor_level<float>(Level<float> &, Panel<float> &&, int, double, int, int, double, Panel<float> &, int *,
                                   hipStream_t);
 
 }  // namespace vb

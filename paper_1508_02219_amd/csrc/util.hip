@@ -1,7 +1,109 @@
-// Prefix sums, fills and small reductions used by every stage.
+// Device memory cache, prefix sums, fills and small reductions used by every stage.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
 #include "common.h"
 
 namespace vb {
+
+// ---------------------------------------------------------------------------------
+// Caching allocator.  Sizes are rounded (256 B below 1 MiB, 2 MiB above) and a free block
+// is reused for a request on the same stream when it is at most a quarter (or 2 MiB)
+// larger, smallest fit first.  When a request misses the cache and would take the memory
+// held (in use + cached) above three quarters of the device, or when hipMalloc fails, the
+// device is synchronized and every cached block goes back to the runtime first.
+// ---------------------------------------------------------------------------------
+namespace {
+struct DevCache {
+    std::mutex mu;
+    std::unordered_map<hipStream_t, std::multimap<size_t, void *>> free_by_stream;
+    std::unordered_map<void *, size_t> live;
+    size_t live_bytes = 0, cached_bytes = 0, peak_bytes = 0;
+    size_t budget = 0;  // three quarters of the device memory, read at the first miss
+    int64_t runtime_allocs = 0;
+
+    static size_t round_size(size_t b) {
+        const size_t small = 256, big = (size_t)2 << 20;
+        return b < ((size_t)1 << 20) ? (b + small - 1) / small * small : (b + big - 1) / big * big;
+    }
+    void release_cached_locked() {
+        (void)hipDeviceSynchronize();
+        for (auto &kv : free_by_stream)
+            for (auto &blk : kv.second) (void)hipFree(blk.second);
+        free_by_stream.clear();
+        cached_bytes = 0;
+    }
+};
+DevCache &dev_cache() {
+    // never destroyed: freeing device memory after the runtime has shut down is unsafe,
+    // and the process exit returns everything anyway
+    static DevCache *c = new DevCache();
+    return *c;
+}
+}  // namespace
+
+void *dev_alloc(size_t bytes, hipStream_t s) {
+    DevCache &c = dev_cache();
+    const size_t want = DevCache::round_size(bytes);
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto fl = c.free_by_stream.find(s);
+    if (fl != c.free_by_stream.end()) {
+        auto it = fl->second.lower_bound(want);
+        const size_t slack = std::max(want / 4, (size_t)2 << 20);
+        if (it != fl->second.end() && it->first <= want + slack) {
+            void *p = it->second;
+            const size_t got = it->first;
+            fl->second.erase(it);
+            c.cached_bytes -= got;
+            c.live[p] = got;
+            c.live_bytes += got;
+            c.peak_bytes = std::max(c.peak_bytes, c.live_bytes);
+            return p;
+        }
+    }
+    if (c.budget == 0) {
+        size_t fr = 0, tot = 0;
+        c.budget = hipMemGetInfo(&fr, &tot) == hipSuccess && tot > 0 ? tot / 4 * 3 : (size_t)-1;
+    }
+    if (c.cached_bytes > 0 && c.live_bytes + c.cached_bytes + want > c.budget) c.release_cached_locked();
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c.release_cached_locked();
+        e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(VBARMS_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+    }
+    ++c.runtime_allocs;
+    c.live[p] = want;
+    c.live_bytes += want;
+    c.peak_bytes = std::max(c.peak_bytes, c.live_bytes);
+    return p;
+}
+
+void dev_free(void *p, hipStream_t s) {
+    if (!p) return;
+    DevCache &c = dev_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;  // not ours: never happens for DBuf
+    const size_t b = it->second;
+    c.live.erase(it);
+    c.live_bytes -= b;
+    c.free_by_stream[s].emplace(b, p);
+    c.cached_bytes += b;
+}
+
+DevCacheStats dev_cache_stats() {
+    DevCache &c = dev_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    return DevCacheStats{c.live_bytes, c.cached_bytes, c.peak_bytes, c.runtime_allocs};
+}
 
 namespace {
 
@@ -54,8 +156,8 @@ template <class Tin, class Tout>
 void scan_impl(const Tin *in, Tout *out, int64_t n, hipStream_t s) {
     int64_t ntiles = (n + kScanTile - 1) / kScanTile;
     if (ntiles == 0) ntiles = 1;
-    int64_t *tsum = nullptr;
-    VB_HIP(hipMallocAsync((void **)&tsum, sizeof(int64_t) * (2 * ntiles + 2), s));
+    DBuf<int64_t> tbuf(2 * ntiles + 2);
+    int64_t *tsum = tbuf.p;
     int64_t *toff = tsum + ntiles + 1;
     k_scan_tile<Tin, Tout><<<(unsigned)ntiles, kScanThreads, 0, s>>>(in, out, tsum, n);
     VB_LAUNCH_CHECK();
@@ -70,7 +172,6 @@ void scan_impl(const Tin *in, Tout *out, int64_t n, hipStream_t s) {
     }
     k_scan_total<Tout><<<1, 1, 0, s>>>(out, toff, n, ntiles);
     VB_LAUNCH_CHECK();
-    VB_HIP(hipFreeAsync(tsum, s));
 }
 
 template <class T>
@@ -139,14 +240,11 @@ void fill_rowblk(const int *rb, int p, int *rowblk, hipStream_t s) {
 }
 int max_block_size(const int *rb, int p, hipStream_t s) {
     if (p <= 0) return 0;
-    int *d = nullptr;
-    VB_HIP(hipMallocAsync((void **)&d, sizeof(int), s));
-    VB_HIP(hipMemsetAsync(d, 0, sizeof(int), s));
-    k_max_block<<<grid_for(p, 256), 256, 0, s>>>(rb, p, d);
+    DBuf<int> d(1);
+    fill_i32(d.p, 0, 1, s);
+    k_max_block<<<grid_for(p, 256), 256, 0, s>>>(rb, p, d.p);
     VB_LAUNCH_CHECK();
-    int m = read_one(d, s);
-    VB_HIP(hipFreeAsync(d, s));
-    return m;
+    return read_one(d.p, s);
 }
 
 }  // namespace vb

@@ -30,7 +30,7 @@ from __future__ import annotations
 import dataclasses
 import numpy as np
 
-__all__ = ["System", "grid_system", "upwind_system", "random_pattern_matrix", "config_system"]
+__all__ = ["System", "grid_system", "upwind_system", "random_pattern_matrix", "dense_rows_matrix", "config_system"]
 
 _M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
 
@@ -244,6 +244,38 @@ def random_pattern_matrix(n: int, density: float, twins: int = 0, seed: int = 0,
     rowptr, col, val = _csr_from_coo(n, rows, cols, vals)
     b = _rhs(n, rowptr, val, "ones", rng)
     return System(n, rowptr, col, val, b, np.ones(n, np.int32), name=f"rand-{n}-{density}-s{seed}")
+
+
+def dense_rows_matrix(n: int, row_len: int = 5, n_dense: int = 4, dense_len: int = 1200, core: int = 1000,
+                      seed: int = 0) -> System:
+    """Sparse random rows plus a few long rows that share a common core of columns.
+
+    Each ordinary row holds its diagonal and ``row_len`` random columns; each long row holds
+    its diagonal, the ``core`` shared columns and random ones up to ``dense_len``.  A long
+    row then meets thousands of other rows through its columns (two-hop neighbours), and
+    the long rows resemble each other (cosine about core / dense_len)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rows_l, cols_l = [], []
+    for i in range(n):
+        c = rng.choice(n, size=row_len, replace=False)
+        rows_l.append(np.full(row_len + 1, i))
+        cols_l.append(np.concatenate([[i], c]))
+    dense = rng.choice(n, size=n_dense, replace=False)
+    shared = rng.choice(n, size=core, replace=False)
+    for i in dense:
+        extra = rng.choice(n, size=dense_len - core, replace=False)
+        c = np.unique(np.concatenate([[i], shared, extra]))
+        rows_l.append(np.full(c.size, i))
+        cols_l.append(c)
+    rows = np.concatenate(rows_l)
+    cols = np.concatenate(cols_l)
+    key = np.unique(rows.astype(np.int64) * n + cols)
+    rows, cols = key // n, key % n
+    vals = rng.standard_normal(rows.size)
+    vals = np.where(rows == cols, 10.0 + np.abs(vals), vals)
+    rowptr, col, val = _csr_from_coo(n, rows, cols, vals)
+    b = _rhs(n, rowptr, val, "ones", rng)
+    return System(n, rowptr, col, val, b, np.ones(n, np.int32), name=f"denserows-{n}-{n_dense}x{dense_len}-s{seed}")
 
 
 def config_system(index: int, scale: float = 1.0) -> System:

@@ -13,11 +13,12 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvbarms.so")
+LIB_PATH = os.environ.get("VBARMS_LIB") or os.path.join(HERE, "libvbarms.so")
 
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_HIP, ERR_OOM, ERR_SINGULAR, ERR_NAN, ERR_STATE = -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
+IS_NATURAL, IS_WEIGHTED = 0, 1
 MAX_LEVELS = 16
 MAX_BLOCK = 32
 # exportable matrices
@@ -50,18 +51,20 @@ class CStats(C.Structure):
 
 class _FParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("droptol", C.c_double * (MAX_LEVELS + 1)), ("drop_schur", C.c_int32),
-                ("precision", C.c_int32)]
+                ("is_order", C.c_int32), ("precision", C.c_int32)]
 
 
 class SInfo(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("true_relres", C.c_double), ("status", C.c_int32)]
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("true_relres", C.c_double), ("status", C.c_int32),
+                ("fp64_refactor", C.c_int32)]
 
 
 class FStats(C.Structure):
     _fields_ = [("compress_ms", C.c_double), ("factor_ms", C.c_double), ("solve_ms", C.c_double),
                 ("factor_level_ms", C.c_double * MAX_LEVELS), ("ilut_ms", C.c_double), ("levels", C.c_int32),
                 ("last_p", C.c_int32), ("factor_values", C.c_int64), ("nnz", C.c_int64),
-                ("spmv_lanes", C.c_int32)]
+                ("spmv_lanes", C.c_int32), ("ilut_waves", C.c_int32), ("ilut_attempts", C.c_int32),
+                ("ilut_result_bytes", C.c_double), ("illcond_blocks", C.c_int32), ("fp64_fallback", C.c_int32)]
 
 
 class KStat(C.Structure):
@@ -82,6 +85,8 @@ SIGNATURES = {
     "vbarms_spmv": (C.c_int, [_P, _P, _P]),
     "vbarms_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, C.c_int32, C.POINTER(SInfo)]),
     "vbarms_get_stats": (C.c_int, [_P, C.POINTER(FStats)]),
+    "vbarms_set_fp64_fallback": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double]),
+    "vbarms_device_memory": (C.c_int, [_P]),
     "vbarms_set_graphs": (C.c_int, [_P, C.c_int32]),
     "vbarms_features": (C.c_int, [_P, C.POINTER(_Csr), _P]),
     "vbarms_mlp_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P]),
@@ -143,6 +148,21 @@ class Exported:
     colidx: np.ndarray
     vals: np.ndarray
     piv: np.ndarray | None
+
+    @property
+    def p(self):
+        return len(self.rb) - 1
+
+    def block(self, k):
+        """Dense block k (row-major) of the exported matrix."""
+        if not hasattr(self, "_voff"):
+            rows = np.repeat(np.arange(self.p), np.diff(self.rowptr))
+            sizes = np.diff(self.rb)[rows].astype(np.int64) * np.diff(self.cb)[np.asarray(self.colidx, np.int64)]
+            self._voff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        i = int(np.searchsorted(self.rowptr, k, side="right") - 1)
+        j = int(self.colidx[k])
+        m, n = self.rb[i + 1] - self.rb[i], self.cb[j + 1] - self.cb[j]
+        return self.vals[self._voff[k]:self._voff[k + 1]].reshape(m, n)
 
 
 class Solver:
@@ -211,7 +231,7 @@ class Solver:
         return st
 
     # -- Steps 2-4 and the last level ---------------------------------------------------
-    def factor(self, levels, droptol, drop_schur=1, precision=F64):
+    def factor(self, levels, droptol, drop_schur=1, precision=F64, is_order=IS_NATURAL):
         p = _FParams()
         p.levels = levels
         dt = np.asarray(droptol, dtype=np.float64).ravel()
@@ -220,6 +240,7 @@ class Solver:
         for i in range(levels + 1):
             p.droptol[i] = float(dt[i])
         p.drop_schur = drop_schur
+        p.is_order = is_order
         p.precision = precision
         self._check(lib().vbarms_factor(self.h, C.byref(p)))
 
@@ -249,6 +270,11 @@ class Solver:
                                 int(restart), int(maxit), C.byref(info))
         self._check(rc, allow_not_converged=True)
         return x, info
+
+    def set_fp64_fallback(self, enable=True, f32_iter_limit=100, min_pivot_ratio=1e-4):
+        """FP32 safeguards: FP64 refactorization on ill-conditioned pivot blocks or stagnation."""
+        self._check(lib().vbarms_set_fp64_fallback(self.h, 1 if enable else 0, int(f32_iter_limit),
+                                                   float(min_pivot_ratio)))
 
     def stats(self):
         st = FStats()
@@ -381,6 +407,15 @@ class Mlp:
 
     def adam_step(self, lr):
         self._check(lib().vbarms_mlp_adam_step(self.h, C.c_float(lr)))
+
+
+def device_memory():
+    """{live, cached, peak, runtime_allocs} of the library's device memory cache (bytes, count)."""
+    out = np.zeros(4, np.int64)
+    rc = lib().vbarms_device_memory(_np_ptr(out))
+    if rc != OK:
+        raise VbarmsError(rc, "vbarms_device_memory failed")
+    return dict(live=int(out[0]), cached=int(out[1]), peak=int(out[2]), runtime_allocs=int(out[3]))
 
 
 def csr_to_device(system, device="cuda"):

@@ -171,6 +171,18 @@ int vbarms_apply(vbarms_t h, const double *x, double *y);
 /* y = A x with the compressed matrix (original numbering, DEVICE vectors). */
 int vbarms_spmv(vbarms_t h, const double *x, double *y);
 
+/* y = A x exactly as vbarms_spmv, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  It
+ * allocates nothing: the permuted copies of x and y live in a fixed array of
+ * 2 * VBARMS_NOALLOC_MAX_N doubles (32 MiB) that the library places on every GPU it runs on
+ * and keeps until the process ends.  x, y: DEVICE vectors of length n (original
+ * numbering), not overlapping.  Every call on one GPU shares that GPU's array, so calls
+ * that overlap in time on one GPU (other handles, other streams) race and must be ordered
+ * by the caller.  Errors: STATE (no compressed matrix), ARG (n > VBARMS_NOALLOC_MAX_N or
+ * NULL vectors). */
+#define VBARMS_NOALLOC_MAX_N (1 << 21)
+int vbarms_spmv_noalloc(vbarms_t h, const double *x, double *y);
+
 /* Solves A x = b by FGMRES(restart) preconditioned on the right with M (Sec. 4.1).
  * b, x: DEVICE vectors of length n in the original numbering; x holds the initial guess
  * on entry (zeros for x0 = 0) and the solution on exit.  Stops when the true relative

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "factor.h"
 
@@ -38,6 +39,34 @@ struct vbarms_ctx {
 };
 
 namespace {
+
+// Fixed device array for vbarms_spmv_noalloc: the permuted input and output vectors of one
+// product (2 * VBARMS_NOALLOC_MAX_N doubles, 32 MiB), one copy per GPU the library runs on,
+// held until the process ends.  Host code never uses the array's name as an address: its
+// device address is read once per device (noalloc_scratch_init) and kept below.
+__device__ __align__(256) double scratch[2 * (size_t)VBARMS_NOALLOC_MAX_N];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Reads the address of `scratch` on the current device (which must be `dev`) once.
+void noalloc_scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) fail(VBARMS_ERR_ARG, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        fail(VBARMS_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = (double *)ptr;
+}
+
+double *noalloc_scratch(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return dev >= 0 && dev < kMaxDevices ? g_scratch_ptr[dev] : nullptr;
+}
 
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
@@ -324,6 +353,7 @@ int vbarms_create(vbarms_t *out, void *hip_stream) {
     h->stream = (hipStream_t)hip_stream;
     int rc = guarded(h, [&] {
         h->err.reset(h->stream);
+        noalloc_scratch_init(h->device);
         return VBARMS_OK;
     });
     if (rc != VBARMS_OK) { delete h; return rc; }
@@ -457,6 +487,24 @@ int vbarms_spmv(vbarms_t h, const double *x, double *y) {
         gather_perm(h->n, h->perm.p, x, h->wx.p, s);
         panel_spmv<double>(h->A, h->wx.p, h->wy.p, s);
         scatter_perm(h->n, h->perm.p, h->wy.p, y, s);
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_spmv_noalloc(vbarms_t h, const double *x, double *y) {
+    return guarded(h, [&] {
+        if (!h->have_A) fail(VBARMS_ERR_STATE, "no compressed matrix");
+        if (h->n > 0 && (!x || !y)) fail(VBARMS_ERR_ARG, "NULL vector");
+        if ((int64_t)h->n > (int64_t)VBARMS_NOALLOC_MAX_N)
+            fail(VBARMS_ERR_ARG, "n = " + std::to_string(h->n) + " exceeds VBARMS_NOALLOC_MAX_N = " +
+                                     std::to_string((int64_t)VBARMS_NOALLOC_MAX_N));
+        double *sx = noalloc_scratch(h->device);
+        if (!sx) fail(VBARMS_ERR_STATE, "no scratch address for this device");
+        double *sy = sx + (size_t)VBARMS_NOALLOC_MAX_N;
+        hipStream_t s = h->stream;
+        gather_perm(h->n, h->perm.p, x, sx, s);
+        panel_spmv<double>(h->A, sx, sy, s);
+        scatter_perm(h->n, h->perm.p, sy, y, s);
         return VBARMS_OK;
     });
 }

@@ -21,6 +21,7 @@ F64, F32 = 0, 1
 IS_NATURAL, IS_WEIGHTED = 0, 1
 MAX_LEVELS = 16
 MAX_BLOCK = 32
+NOALLOC_MAX_N = 1 << 21
 # exportable matrices
 M_A, M_AS, M_G, M_W, M_D, M_LAST, M_L, M_U, M_DL = range(9)
 # timed kernel classes
@@ -83,6 +84,7 @@ SIGNATURES = {
     "vbarms_error_location": (C.c_int, [_P, _P, _P]),
     "vbarms_apply": (C.c_int, [_P, _P, _P]),
     "vbarms_spmv": (C.c_int, [_P, _P, _P]),
+    "vbarms_spmv_noalloc": (C.c_int, [_P, _P, _P]),
     "vbarms_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, C.c_int32, C.POINTER(SInfo)]),
     "vbarms_get_stats": (C.c_int, [_P, C.POINTER(FStats)]),
     "vbarms_set_fp64_fallback": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double]),
@@ -261,6 +263,12 @@ class Solver:
         y = torch.empty_like(x) if out is None else out
         self._check(lib().vbarms_spmv(self.h, _dev_ptr(x, torch.float64), _dev_ptr(y, torch.float64)))
         return y
+
+    def spmv_noalloc(self, x, out):
+        """y = A x through the allocation-free entry point (out must be preallocated)."""
+        torch = self._torch
+        self._check(lib().vbarms_spmv_noalloc(self.h, _dev_ptr(x, torch.float64), _dev_ptr(out, torch.float64)))
+        return out
 
     def solve(self, b, x0=None, tol=1e-8, restart=30, maxit=1000):
         torch = self._torch

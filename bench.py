@@ -83,6 +83,50 @@ def _cpu_baseline(wl, n_full):
             "host_cpu": model, "host_logical_cpus": ncpu}
 
 
+def _comparators(wl, side, V, torch):
+    """Sec. 4 comparison (Table 5's claim): the same system solved with VBARMS, with block
+    ILUT alone on the compressed blocks (VBILUT) and with pointwise ILUT; median of three
+    timed runs each after one warm-up, FP64."""
+    system = wl["make"](side)
+    dev = V.csr_to_device(system)
+    b = torch.as_tensor(system.b, device="cuda")
+    n = system.n
+    single_perm = torch.arange(n, dtype=torch.int32, device="cuda")
+    single_bptr = torch.arange(n + 1, dtype=torch.int32, device="cuda")
+    methods = {"VBARMS": (wl["levels"], False), "VBILUT": (0, False), "ILUT (pointwise)": (0, True)}
+    out = {"comparators": {}, "workload": wl["desc"].replace("74^3", f"{side}^3").replace("40^3", f"{side}^3"),
+           "n": n, "nnz": system.nnz, "tau": wl["tau"], "droptol": wl["droptol"], "krylov": f"FGMRES({wl['restart']})"}
+    for name, (lev, pointwise) in methods.items():
+        sv = V.Solver()
+        runs = []
+        for k in range(4):
+            t0 = time.perf_counter()
+            if pointwise:
+                st = sv.set_partition(*dev, single_perm, single_bptr)
+            else:
+                _, _, st = sv.compress(*dev, wl["tau"])
+            sv.factor(lev, wl["droptol"])
+            x, info = sv.solve(b, tol=TOL, restart=wl["restart"], maxit=MAXIT)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            fs = sv.stats()
+            if k > 0:
+                runs.append((dt, fs, info, st))
+            print(f"[comparators] {name} run {k}: {dt * 1e3:.1f} ms its {info.iters} status {info.status}",
+                  file=sys.stderr, flush=True)
+        runs.sort(key=lambda r: r[0])
+        dt, fs, info, st = runs[1]
+        out["comparators"][name] = {
+            "s_per_solve": round(dt, 4), "iters": info.iters, "converged": info.status == 0,
+            "true_relres": info.true_relres, "blocks": st.nblocks, "av_bd": round(st.av_bd, 4),
+            "compress_ms": round(fs.compress_ms, 2), "factor_ms": round(fs.factor_ms, 2),
+            "solve_ms": round(fs.solve_ms, 2), "levels": fs.levels, "last_level_blocks": fs.last_p,
+            "ilut_waves": fs.ilut_waves, "mem_ratio": round(fs.factor_values / max(fs.nnz, 1), 3)}
+        sv.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +137,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (the reference for counter scaling)")
+    ap.add_argument("--comparators", type=int, default=0, metavar="SIDE",
+                    help="instead of the benchmark, compare VBARMS with block ILUT alone (VBILUT, levels = 0) and "
+                         "with pointwise ILUT (1x1 blocks, levels = 0) on a SIDE^3 grid of the workload's recipe")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the whole problem fits on one MI355X and this build has no "
@@ -118,6 +165,8 @@ def main() -> int:
         return 0
     wl = WORKLOADS[args.workload]
     tau, levels, droptol, restart = wl["tau"], wl["levels"], wl["droptol"], wl["restart"]
+    if args.comparators:
+        return _comparators(wl, args.comparators, V, torch)
     system = wl["make"](wl["side"])
     print(f"[bench] workload {system.name} n={system.n} nnz={system.nnz}", file=sys.stderr, flush=True)
     rp, ci, va = V.csr_to_device(system)

@@ -210,43 +210,62 @@ __global__ void __launch_bounds__(kSimThreads) k_sim_global(int nbig, const int 
     }
 }
 
-// One round of the lexicographically first independent set: a vertex enters when all its
-// lower neighbours are out, leaves when one of them is in.  `eptr/elist` hold lower
-// neighbours only; `elist2` (optional) a second lower-neighbour list.  Monotone, so races
-// between rounds only speed convergence.
-// true when u comes before v in the visiting order: ascending index, or with weights,
-// descending weight and ascending index among equal weights
+// Lexicographically first independent set by rounds (state 1 in, 2 out).  Decisions are
+// monotone, so a state read while another thread writes it only speeds convergence.
+// visits_before: true when u comes before v in the visiting order: ascending index, or with
+// weights, descending weight and ascending index among equal weights
 __device__ inline bool visits_before(int u, int v, const double *prio) {
     if (!prio) return u < v;
     const double wu = prio[u], wv = prio[v];
     return wu > wv || (wu == wv && u < v);
 }
 
-__global__ void k_lfmis_round(int nv, const int64_t *eptr, const int *elist, const int64_t *eptr2,
-                              const int *elist2, const double *prio, int *state, int *undecided) {
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
+// Neighbours of v visited before v (from one or two adjacency lists, duplicates kept),
+// counted (pass 0) and listed (pass 1); the rounds then read only these.
+__global__ void k_lfmis_before(int nv, const int64_t *eptr, const int *elist, const int64_t *eptr2, const int *elist2,
+                               const double *prio, const int64_t *bptr, int *bcnt, int *blist) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nv) return;
+    int c = 0;
+    int64_t o = bptr ? bptr[v] : 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int64_t *ep = pass == 0 ? eptr : eptr2;
+        const int *el = pass == 0 ? elist : elist2;
+        if (!el) continue;
+        for (int64_t e = ep[v]; e < ep[v + 1]; ++e) {
+            const int u = el[e];
+            if (u == v || !visits_before(u, v, prio)) continue;
+            if (blist) blist[o + c] = u;
+            ++c;
+        }
+    }
+    if (!blist) bcnt[v] = c;
+}
+
+// One round over the vertices of `list` (count nl): a vertex enters when all its earlier
+// neighbours are out and leaves when one of them is in.  The states of eight neighbours are
+// loaded before any is examined, so a round costs a few dependent loads per vertex.
+__global__ void k_lfmis_round(int nl, const int *list, const int64_t *bptr, const int *blist, int *state) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nl) return;
+    const int v = list[q];
     if (__atomic_load_n(&state[v], __ATOMIC_RELAXED) != 0) return;
     bool any_in = false, all_out = true;
-    for (int64_t e = eptr[v]; e < eptr[v + 1]; ++e) {
-        int u = elist[e];
-        if (u == v || !visits_before(u, v, prio)) continue;
-        int s = __atomic_load_n(&state[u], __ATOMIC_RELAXED);
-        if (s == 1) { any_in = true; break; }
-        if (s != 2) all_out = false;
-    }
-    if (!any_in && elist2) {
-        for (int64_t e = eptr2[v]; e < eptr2[v + 1]; ++e) {
-            int u = elist2[e];
-            if (u == v || !visits_before(u, v, prio)) continue;
-            int s = __atomic_load_n(&state[u], __ATOMIC_RELAXED);
-            if (s == 1) { any_in = true; break; }
-            if (s != 2) all_out = false;
+    const int64_t e1 = bptr[v + 1];
+    for (int64_t e0 = bptr[v]; e0 < e1 && !any_in; e0 += 8) {
+        int st[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) st[u] = e0 + u < e1 ? blist[e0 + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) st[u] = st[u] >= 0 ? __atomic_load_n(&state[st[u]], __ATOMIC_RELAXED) : 2;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            any_in = any_in || st[u] == 1;
+            all_out = all_out && st[u] == 2;
         }
     }
     if (any_in) __atomic_store_n(&state[v], 2, __ATOMIC_RELAXED);
     else if (all_out) __atomic_store_n(&state[v], 1, __ATOMIC_RELAXED);
-    else if (undecided) atomicAdd(undecided, 1);
 }
 
 __global__ void k_assign_rep(int nr, const int *replist, const int64_t *eptr, const int *elist, const int *state,
@@ -288,24 +307,58 @@ __global__ void k_group_sort(int p, const int *bptr, int *perm) {
     }
 }
 
+// undecided vertices of list_in appended to list_out (one atomic per wavefront)
+__global__ void k_lfmis_compact(int nl, const int *list_in, const int *state, int *list_out, int *cnt_out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = q < nl ? list_in[q] : -1;
+    const bool keep = v >= 0 && state[v] == 0;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long mask = __ballot(keep);
+    const int tot = __popcll(mask);
+    int base = 0;
+    if (tot > 0) {
+        const int leader = __ffsll((long long)mask) - 1;
+        if (lane == leader) base = atomicAdd(cnt_out, tot);
+        base = __shfl(base, leader, 64);
+    }
+    if (keep) list_out[base + __popcll(mask & ((1ull << lane) - 1ull))] = v;
+}
+
 }  // namespace
 
-// Lexicographically first MIS by rounds; shared with the independent-set step.
+// Lexicographically first MIS by rounds; shared with the independent-set step.  Every
+// round visits only the vertices that were undecided at the last compaction (every
+// `batch` rounds): a decision never changes, so skipping decided vertices changes nothing.
 void lfmis(int nv, const int64_t *eptr, const int *elist, const int64_t *eptr2, const int *elist2, const double *prio,
            int *state, hipStream_t s) {
     fill_i32(state, 0, nv, s);
     if (nv == 0) return;
-    DBuf<int> und(1);
+    // each vertex's earlier-visited neighbours, listed once
+    DBuf<int> bcnt(nv);
+    DBuf<int64_t> bptr(nv + 1);
+    k_lfmis_before<<<grid_for(nv, 256), 256, 0, s>>>(nv, eptr, elist, eptr2, elist2, prio, nullptr, bcnt.p, nullptr);
+    VB_LAUNCH_CHECK();
+    const int64_t nb = scan_i32_to_i64(bcnt.p, bptr.p, nv, s);
+    DBuf<int> blist(std::max<int64_t>(nb, 1));
+    k_lfmis_before<<<grid_for(nv, 256), 256, 0, s>>>(nv, eptr, elist, eptr2, elist2, prio, bptr.p, nullptr, blist.p);
+    VB_LAUNCH_CHECK();
+    DBuf<int> lists(2 * (size_t)nv), cnt(2);
+    iota_i32(lists.p, nv, s);
+    int nl = nv, cur = 0;
     const int batch = 8;
     for (int round = 0;; round += batch) {
+        const int *lin = lists.p + (size_t)cur * nv;
         for (int b = 0; b < batch; ++b) {
-            bool last = b == batch - 1;
-            if (last) VB_HIP(hipMemsetAsync(und.p, 0, sizeof(int), s));
-            k_lfmis_round<<<grid_for(nv, 256), 256, 0, s>>>(nv, eptr, elist, eptr2, elist2, prio, state,
-                                                             last ? und.p : nullptr);
+            k_lfmis_round<<<grid_for(nl, 256), 256, 0, s>>>(nl, lin, bptr.p, blist.p, state);
             VB_LAUNCH_CHECK();
         }
-        if (read_one(und.p, s) == 0) break;
+        int *lout = lists.p + (size_t)(1 - cur) * nv;
+        fill_i32(cnt.p, 0, 1, s);
+        k_lfmis_compact<<<grid_for(nl, 256), 256, 0, s>>>(nl, lin, state, lout, cnt.p);
+        VB_LAUNCH_CHECK();
+        nl = read_one(cnt.p, s);
+        if (nl == 0) break;
+        cur = 1 - cur;
         if (round > 4 * nv + 64) fail(VBARMS_ERR_HIP, "independent-set rounds did not converge");
     }
 }

@@ -105,11 +105,13 @@ template <class T>
 void factor_level(Level<T> &L, Panel<T> &&A, int lvl, double droptol, int drop_schur, int is_order, double min_ratio,
                   Panel<T> &next, int *err, hipStream_t s);
 // Room reserved by the block ILUT, kept by the caller across factorizations: working rows
-// hold `grow` times their input row; the L and U pools hold `pool` times the input's blocks
-// and values each.  Both only grow, when an attempt runs out of room.
+// hold `grow` times their input row (and at least `grow` times the mean row); the L and U
+// pools hold `pool` times the input's blocks and values each; a row's block list in LDS
+// holds `rbcap` entries.  All only grow, when an attempt runs out of room.
 struct IlutHint {
     int grow = 4;
     double pool = 1.5;
+    int rbcap = 256;  // block-list entries a row may hold in LDS
 };
 // Block ILUT of `last.A` with threshold t.
 template <class T>

@@ -34,6 +34,9 @@ namespace {
 #ifndef VB_ILUT_STEPCAP
 #define VB_ILUT_STEPCAP 8
 #endif
+#ifndef VB_ILUT_MINWAVES
+#define VB_ILUT_MINWAVES 1
+#endif
 constexpr int kIlutThreads = VB_ILUT_THREADS;
 static_assert(kIlutThreads % 64 == 0, "whole wavefronts");
 constexpr int kMaxRowBlocks = 1024;  // largest block list of one working row
@@ -196,7 +199,7 @@ __device__ inline void stage_tile(T *dst, const T *src, int64_t ld, int rows, in
 // the gather kernel of a later launch returns it to the ready list once k has finished.
 template <class T>
 __device__ void ilut_row(
-    const int i, int launch, int min_ready, int p, int *wait_out, int *cnt_wait_out, int *wait_on, int *nfinished,
+    const int i, int launch, int min_ready, int p, int2 *wait_out, int *cnt_wait_out, int *nfinished,
     const int *rb, const int64_t *rp, const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av,
     double droptol, double min_ratio, int *done, RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols,
     int *woffs, unsigned char *west, T *wvals, T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec, int *lci,
@@ -240,6 +243,18 @@ __device__ void ilut_row(
     T *w = wvals + V0;
     // the column map packs a w offset with the block width (6 bits)
     const bool use_map = CV < ((int64_t)1 << 25);
+    // the first kSpecEntries saved list entries are loaded together with the row state (a
+    // row's list region holds at least 64 entries; on a first visit they are not used)
+    constexpr int kSpecEntries = 64;
+    static_assert(kSpecEntries <= kIlutThreads, "one speculative entry per thread");
+    const bool spec = t < kSpecEntries && t < CB;
+    int spec_c = 0, spec_o = 0;
+    unsigned char spec_s = 0;
+    if (spec) {
+        spec_c = cols[t];
+        spec_o = offs[t];
+        spec_s = est[t];
+    }
     if (t == 0) {
         RowState r = rs[i];
         s_nb = r.nb;
@@ -250,8 +265,11 @@ __device__ void ilut_row(
         if (r.status == 0) {
             int nA = (int)(rp[i + 1] - rp[i]);
             int64_t W = wp[i + 1] - wp[i];
-            if (nA > CB || nA > kRowCap || m > lds.maxm || (int64_t)m * W > CV) {
-                dev_set_error(err, VBARMS_ERR_OOM, lvl, i);
+            if (nA > CB || m > lds.maxm || (int64_t)m * W > CV) {
+                dev_set_error(err, VBARMS_ERR_OOM, lvl, i);  // the row's own room
+                s_stop = 1;
+            } else if (nA > kRowCap) {
+                dev_set_error(err, VBARMS_ERR_OOM, lvl, -2 - i);  // the LDS block list
                 s_stop = 1;
             }
             s_nb = nA;
@@ -276,13 +294,19 @@ __device__ void ilut_row(
             s_uc0[e] = c0;
         }
     } else {
-        // resumed row: the saved list, four entries per thread loaded before any is stored
-        for (int e0 = 0; e0 < s_nb; e0 += 4 * kIlutThreads) {
+        // resumed row: the saved list; the speculative entries first, then the rest, four
+        // entries per thread loaded before any is stored
+        if (spec && t < s_nb) {
+            l_cols[t] = spec_c;
+            l_offs[t] = spec_o;
+            l_est[t] = spec_s;
+        }
+        for (int e0 = 0; e0 + kSpecEntries < s_nb; e0 += 4 * kIlutThreads) {
             int cv[4], ov[4];
             unsigned char sv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int e = e0 + u * kIlutThreads + t;
+                const int e = kSpecEntries + e0 + u * kIlutThreads + t;
                 cv[u] = ov[u] = 0;
                 sv[u] = 0;
                 if (e < s_nb) {
@@ -293,7 +317,7 @@ __device__ void ilut_row(
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int e = e0 + u * kIlutThreads + t;
+                const int e = kSpecEntries + e0 + u * kIlutThreads + t;
                 if (e < s_nb) {
                     l_cols[e] = cv[u];
                     l_offs[e] = ov[u];
@@ -380,8 +404,7 @@ __device__ void ilut_row(
                 rs[i] = RowState{s_nb, s_used, last, 1};
                 nbytes += 8ull * (s_nb - s_nb0) + s_nb + 24;
                 // wait on row k; everything written here is read in a later launch
-                wait_on[i] = k;
-                wait_out[atomicAdd(cnt_wait_out, 1)] = i;
+                wait_out[atomicAdd(cnt_wait_out, 1)] = make_int2(i, k);
                 atomicAdd(moved, nbytes);
             }
             return;
@@ -461,7 +484,8 @@ __device__ void ilut_row(
             int e = atomicAdd(&s_nb, 1);
             int off = atomicAdd(&s_used, m * nJ);
             if (e >= CB || e >= kRowCap || (int64_t)off + m * nJ > CV) {
-                dev_set_error(err, VBARMS_ERR_OOM, lvl, i);
+                // the row's own room (block >= 0) or the LDS block list (block <= -2) is full
+                dev_set_error(err, VBARMS_ERR_OOM, lvl, e >= CB || (int64_t)off + m * nJ > CV ? i : -2 - i);
                 s_stop = 1;
                 continue;
             }
@@ -627,52 +651,90 @@ __device__ void ilut_row(
 }
 
 // Gather of a launch: waiting rows whose awaited row has finished (in an earlier launch)
-// move to the ready list, the others stay on the waiting list.  Rows that never ran wait
-// on nothing (-1).
-// Appends are aggregated per wavefront (one atomic per list and wavefront).
-__device__ inline int wave_append(bool take, int *counter) {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long mask = __ballot(take);
-    const int total = __popcll(mask);
-    int base = 0;
-    if (total > 0) {
-        const int leader = __ffsll((long long)mask) - 1;
-        if (lane == leader) base = atomicAdd(counter, total);
-        base = __shfl(base, leader, 64);
-    }
-    return base + __popcll(mask & ((1ull << lane) - 1ull));
-}
+// move to the ready list, the others stay on the waiting list.  A waiting entry is the pair
+// (row, awaited row); rows that never ran await nothing (-1).  Each workgroup takes 1024
+// consecutive entries at a time, four per thread with all loads issued before use, and
+// appends them with one atomic per list (positions from wavefront ballots and an LDS scan
+// over the wavefronts).
+constexpr int kGatherThreads = 256;
+constexpr int kGatherItems = 4;
 
-__global__ void __launch_bounds__(256) k_ilut_gather(const int *wait_in, const int *cnt_wait_in, const int *wait_on,
-                                                     const int *done, int *ready, int *cnt_ready, int *wait_out,
-                                                     int *cnt_wait_out, int *min_ready) {
+__global__ void __launch_bounds__(kGatherThreads) k_ilut_gather(const int2 *wait_in, const int *cnt_wait_in,
+                                                                const int *done, int *ready, int *cnt_ready,
+                                                                int2 *wait_out, int *cnt_wait_out, int *min_ready) {
+    constexpr int NW = kGatherThreads / 64;
+    __shared__ int s_tr[NW], s_tw[NW], s_br[NW], s_bw[NW], s_mn[NW];
     const int n = *cnt_wait_in;
-    const int stride = gridDim.x * blockDim.x;
-    // every lane of a wavefront takes part in each round, so the ballots see all of them
-    for (int e0 = blockIdx.x * blockDim.x; e0 < n; e0 += stride) {
-        const int e = e0 + (int)threadIdx.x;
-        int i = -1;
-        bool rdy = false;
-        if (e < n) {
-            i = wait_in[e];
-            const int k = wait_on[i];
-            rdy = k < 0 || done[k] != 0;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    constexpr int tile = kGatherThreads * kGatherItems;
+    for (int b0 = blockIdx.x * tile; b0 < n; b0 += gridDim.x * tile) {
+        int2 ent[kGatherItems];
+        bool has[kGatherItems], rdy[kGatherItems];
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) {
+            const int e = b0 + u * kGatherThreads + t;
+            has[u] = e < n;
+            ent[u] = has[u] ? wait_in[e] : make_int2(-1, -1);
         }
-        const int pr = wave_append(e < n && rdy, cnt_ready);
-        const int pw = wave_append(e < n && !rdy, cnt_wait_out);
-        if (e < n) {
-            if (rdy) ready[pr] = i;
-            else wait_out[pw] = i;
+        int dk[kGatherItems];
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) dk[u] = has[u] && ent[u].y >= 0 ? done[ent[u].y] : 1;
+        int pr[kGatherItems], pw[kGatherItems];
+        int tr = 0, tw = 0, mn = INT_MAX;
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) {
+            rdy[u] = has[u] && dk[u] != 0;
+            const unsigned long long mr = __ballot(rdy[u]), mw = __ballot(has[u] && !rdy[u]);
+            pr[u] = tr + __popcll(mr & lt);
+            pw[u] = tw + __popcll(mw & lt);
+            tr += __popcll(mr);
+            tw += __popcll(mw);
+            if (rdy[u] && ent[u].x < mn) mn = ent[u].x;
         }
-        // smallest row moved to the ready list (one atomic per wavefront)
-        int mn = e < n && rdy ? i : INT_MAX;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             const int o = __shfl_xor(mn, off, 64);
             mn = o < mn ? o : mn;
         }
-        if ((threadIdx.x & 63) == 0 && mn != INT_MAX) atomicMin(min_ready, mn);
+        if (lane == 0) {
+            s_tr[wv] = tr;
+            s_tw[wv] = tw;
+            s_mn[wv] = mn;
+        }
+        __syncthreads();
+        if (t == 0) {
+            int ar = 0, aw = 0, m = INT_MAX;
+            for (int q = 0; q < NW; ++q) {
+                s_br[q] = ar;
+                s_bw[q] = aw;
+                ar += s_tr[q];
+                aw += s_tw[q];
+                m = s_mn[q] < m ? s_mn[q] : m;
+            }
+            const int base_r = ar > 0 ? atomicAdd(cnt_ready, ar) : 0;
+            const int base_w = aw > 0 ? atomicAdd(cnt_wait_out, aw) : 0;
+            for (int q = 0; q < NW; ++q) {
+                s_br[q] += base_r;
+                s_bw[q] += base_w;
+            }
+            if (m != INT_MAX) atomicMin(min_ready, m);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) {
+            if (!has[u]) continue;
+            if (rdy[u]) ready[s_br[wv] + pr[u]] = ent[u].x;
+            else wait_out[s_bw[wv] + pw[u]] = ent[u];
+        }
+        __syncthreads();  // s_br / s_bw are rewritten by the next tile
     }
+}
+
+// waiting list of the first launch: every row, awaiting nothing
+__global__ void k_wait_init(int p, int2 *w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p) w[i] = make_int2(i, -1);
 }
 
 // One launch: a fixed grid strides over the ready list.  Counter slots: the gather of
@@ -680,10 +742,10 @@ __global__ void __launch_bounds__(256) k_ilut_gather(const int *wait_in, const i
 // clears the ready count of launch L+1 and the waiting count launch L+1 will append to,
 // both last read by launch L-1.
 template <class T>
-__global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
+__global__ void __launch_bounds__(kIlutThreads, VB_ILUT_MINWAVES) k_ilut_wave(
     int launch, int p, const int *ready, const int *cnt_ready, int *cnt_ready_clear, const int *min_ready_in,
-    int *min_ready_clear, int *wait_out,
-    int *cnt_wait_out, int *cnt_wait_clear, int *wait_on, int *nfinished, const int *rb, const int64_t *rp,
+    int *min_ready_clear, int2 *wait_out,
+    int *cnt_wait_out, int *cnt_wait_clear, int *nfinished, const int *rb, const int64_t *rp,
     const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av, double droptol, double min_ratio,
     int *done, RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols, int *woffs, unsigned char *west,
     T *wvals,
@@ -698,7 +760,7 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
     const int nin = *cnt_ready;
     const int min_ready = *min_ready_in;
     for (int slot = blockIdx.x; slot < nin; slot += gridDim.x) {
-        ilut_row<T>(ready[slot], launch, min_ready, p, wait_out, cnt_wait_out, wait_on, nfinished, rb, rp, ci, co, wp, vp, av,
+        ilut_row<T>(ready[slot], launch, min_ready, p, wait_out, cnt_wait_out, nfinished, rb, rp, ci, co, wp, vp, av,
                     droptol, min_ratio, done, rs, boff, voff, wcols, woffs, west, wvals, dl, dl_off, dl_piv, rec, lci,
                     lco, lv, uci,
                     uco, uv, cursors, capb_pool, capv_pool, err, lvl, moved, lds);
@@ -706,16 +768,18 @@ __global__ void __launch_bounds__(kIlutThreads) k_ilut_wave(
     }
 }
 
-// capacities of the per-row working rows: `grow` times the input row
-__global__ void k_row_caps(int p, const int *rb, const int64_t *rp, const int64_t *wp, int grow, int64_t *capb,
-                           int64_t *capv) {
+// capacities of the per-row working rows: `grow` times the input row, and at least `grow`
+// times the mean input row (blocks, panel columns), so that short rows that fill up do not
+// force a retry
+__global__ void k_row_caps(int p, const int *rb, const int64_t *rp, const int64_t *wp, int grow, int64_t floor_b,
+                           int64_t floor_w, int64_t *capb, int64_t *capv) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p) return;
     int64_t nA = rp[i + 1] - rp[i];
     int64_t m = rb[i + 1] - rb[i];
     int64_t W = wp[i + 1] - wp[i];
-    capb[i] = std::min<int64_t>(kMaxRowBlocks, std::max<int64_t>(64, grow * nA));
-    capv[i] = std::max<int64_t>(m * 64, grow * m * W);
+    capb[i] = std::min<int64_t>(kMaxRowBlocks, std::max<int64_t>(std::max<int64_t>(64, floor_b), grow * nA));
+    capv[i] = m * std::max<int64_t>(std::max<int64_t>(64, floor_w), grow * W);
 }
 
 __global__ void k_rec_counts(int p, const IlutRowRec *rec, int which, int64_t *cnt) {
@@ -916,7 +980,8 @@ void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, 
         const int grow = hint.grow;
         // per-row working rows
         DBuf<int64_t> capb(p), capv(p), boff(p + 1), voff(p + 1);
-        k_row_caps<<<grid_for(p, 256), 256, 0, s>>>(p, A.rb.p, A.rp.p, A.wp.p, grow, capb.p, capv.p);
+        const int64_t floor_b = (int64_t)grow * ((A.nb + p - 1) / p), floor_w = (int64_t)grow * ((A.nw + p - 1) / p);
+        k_row_caps<<<grid_for(p, 256), 256, 0, s>>>(p, A.rb.p, A.rp.p, A.wp.p, grow, floor_b, floor_w, capb.p, capv.p);
         VB_LAUNCH_CHECK();
         int64_t totb = scan_i64(capb.p, boff.p, p, s);
         int64_t totv = scan_i64(capv.p, voff.p, p, s);
@@ -939,21 +1004,30 @@ void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, 
         // LDS of the wave kernel: the largest working-row list this attempt allows
         IlutLds lds;
         lds.maxm = A.maxm;
-        lds.rbcap = (int)std::min<int64_t>(kMaxRowBlocks, std::max<int64_t>(64, grow * max_na));
+        // the block list held in LDS: its own capacity, independent of the rows' room in
+        // global memory, so that the LDS of a workgroup (and with it the workgroups resident
+        // per CU) does not grow with that room
+        {
+            int cap = std::max(hint.rbcap, 64);
+            while (cap < 2 * max_na && cap < kMaxRowBlocks) cap *= 2;
+            lds.rbcap = std::min(cap, kMaxRowBlocks);
+        }
         // hash load stays below two thirds, and a free slot always ends a probe
         lds.hcap = 64;
         while (2 * lds.hcap < 3 * lds.rbcap) lds.hcap *= 2;
         lds.ustage = kUStage;
         const size_t lds_bytes = ilut_lds_bytes<T>(lds);
         // cnt: three rotating waiting-list counters, two ready counters, finished rows
-        DBuf<int> done(p), waits(2 * (size_t)p), ready(p), wait_on(p), cnt(8);
+        DBuf<int> done(p), ready(p), cnt(8);
+        DBuf<int2> waits(2 * (size_t)p);
         DBuf<unsigned long long> moved(1);
         fill_val<unsigned long long>(moved.p, 0ull, 1, s);
         VB_HIP(hipMemsetAsync(rs.p, 0, sizeof(RowState) * p, s));
         fill_i64(cursors.p, 0, 4, s);
         fill_i32(done.p, 0, p, s);
-        fill_i32(wait_on.p, -1, p, s);
-        iota_i32(waits.p + p, p, s);  // waiting list of launch 1 (odd launches read the second list)
+        // waiting list of launch 1 (odd launches read the second list)
+        k_wait_init<<<grid_for(p, 256), 256, 0, s>>>(p, waits.p + p);
+        VB_LAUNCH_CHECK();
         // waiting counts (3), ready counts (2), finished rows, smallest ready row (2)
         const int cnt0[8] = {0, p, 0, 0, 0, 0, INT_MAX, INT_MAX};
         to_device(cnt.p, cnt0, 8, s);
@@ -968,9 +1042,9 @@ void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, 
             if (launch > p + kCheckEvery) fail(VBARMS_ERR_HIP, "block ILUT made no progress");
             for (int q = 0; q < kCheckEvery; ++q) {
                 ++launch;
-                const int *w_in = waits.p + (size_t)(launch & 1) * p;
-                int *w_out = waits.p + (size_t)((launch + 1) & 1) * p;
-                k_ilut_gather<<<kGatherBlocks, 256, 0, s>>>(w_in, cw + launch % 3, wait_on.p, done.p, ready.p,
+                const int2 *w_in = waits.p + (size_t)(launch & 1) * p;
+                int2 *w_out = waits.p + (size_t)((launch + 1) & 1) * p;
+                k_ilut_gather<<<kGatherBlocks, kGatherThreads, 0, s>>>(w_in, cw + launch % 3, done.p, ready.p,
                                                             cr + launch % 2, w_out, cw + (launch + 1) % 3,
                                                             mr + launch % 2);
                 VB_LAUNCH_CHECK();
@@ -978,7 +1052,7 @@ void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, 
                 k_ilut_wave<T><<<grid, kIlutThreads, lds_bytes, s>>>(
                     launch, p, ready.p, cr + launch % 2, cr + (launch + 1) % 2, mr + launch % 2, mr + (launch + 1) % 2,
                     w_out, cw + (launch + 1) % 3,
-                    cw + (launch + 2) % 3, wait_on.p, nfin, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p,
+                    cw + (launch + 2) % 3, nfin, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p, A.v.p,
                     droptol, min_ratio, done.p, rs.p, boff.p, voff.p, wcols.p, woffs.p, west.p, wvals.p, last.dl.p,
                     last.dl_off.p, last.dl_piv.p, rec.p, lci.p, lco.p, lv.p, uci.p, uco.p, uv.p, cursors.p, capb_pool,
                     capv_pool, err, lvl, moved.p, lds);
@@ -1003,10 +1077,13 @@ void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, 
             if (kt && kt->on) kt->tot[VBARMS_K_ILUT].bytes += (double)read_one(moved.p, s);
         }
         if (code == VBARMS_ERR_OOM && attempt < 9) {
-            // a working row (eblock >= 0) or a pool (eblock < 0) ran out of room: start again
-            // with more, and keep the larger size for the next factorization on this handle
+            // a working row (eblock >= 0), a pool (eblock == -1) or the LDS block list
+            // (eblock <= -2) ran out of room: start again with more, and keep the larger
+            // size for the next factorization on this handle
             if (eblock >= 0) hint.grow *= 2;
-            else hint.pool *= 2.0;
+            else if (eblock == -1) hint.pool *= 2.0;
+            else if (lds.rbcap < kMaxRowBlocks) hint.rbcap = 2 * lds.rbcap;
+            else fail(VBARMS_ERR_OOM, "a last-level row has more than 1024 blocks");
             continue;
         }
         if (code != 0) return;  // reported by the caller from the error record

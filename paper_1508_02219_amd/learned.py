@@ -7,13 +7,23 @@ training matrices (compress + factor + FGMRES on the GPU), and the network's for
 backpropagation and Adam update (``vbarms_mlp_*``).  This file only orchestrates.
 
 Label of a matrix: the (tau, t) of the sweep grid with the smallest measured
-time-to-solve among the settings that reach the tolerance.  Target vector:
-[tau, log10 t_0, ..., log10 t_L] (the sweep uses one t for every level).  Without a
-trained network the defaults tau = 0.7 and t = 1e-4 apply.
+time-to-solve among the settings that reach the tolerance, then refined level by level:
+each level's t (and the last level's) is moved by a factor of 10 up or down, and a move
+is kept when it is faster by more than 2%.  Target vector: [tau, log10 t_0, ...,
+log10 t_L].  Without a trained network the defaults tau = 0.7 and t = 1e-4 apply.
+
+``python -m paper_1508_02219_amd.learned --out FILE`` labels the training set on the GPU
+(the recipe of the learned-selection workload: upwind grids of 20^3 to 34^3 nodes, a
+fixed block size of 4, 5 or 6 per matrix, Peclet LogUniform(0.1, 1000), z-link
+anisotropy 1..100, 0-20% block perturbation) and writes it as JSON.
 """
 from __future__ import annotations
 
+import argparse
+import json
 import math
+import sys
+import time
 from dataclasses import dataclass
 
 import numpy as np
@@ -24,76 +34,111 @@ from . import vbarms as V
 TAUS = (0.6, 0.7, 0.8, 0.9, 1.0)
 TOLS = (1e-5, 1e-4, 1e-3, 1e-2)
 DEFAULT_TAU, DEFAULT_TOL = 0.7, 1e-4
+LEVELS = 3
+RESTART, RTOL, MAXIT = 50, 1e-8, 400
 HIDDEN, DEPTH = 128, 3
+FAIL_RATIO = 10.0  # a setting that does not converge counts as 10x the best time
 
 
 @dataclass
 class RunResult:
     tau: float
-    tol: float
+    tols: tuple
     ok: bool
     iters: int
     ms: float          # compress + factor + solve, device time
     relres: float
 
 
-def training_system(seed: int, side_range=(6, 10)):
-    """A matrix of the training distribution: upwind grid, fixed block size per matrix,
-    Peclet LogUniform(0.1, 1000), anisotropy 1..100 on z-links, 0-20% block perturbation."""
+def recipe(seed: int, side_range=(20, 34)):
+    """Parameters of one matrix of the training distribution (seeded)."""
     rng = np.random.default_rng(10_000 + seed)
-    side = int(rng.integers(side_range[0], side_range[1] + 1))
-    ell = int(rng.choice([4, 5, 6]))
-    aniso = float(np.exp(rng.uniform(0.0, np.log(100.0))))
-    pert = float(rng.uniform(0.0, 0.2))
-    return synth.upwind_system(side, side, side, ell_choices=(ell,), pe_range=(0.1, 1000.0), anisotropy=aniso,
-                               perturb=pert, seed=seed)
+    return dict(side=int(rng.integers(side_range[0], side_range[1] + 1)), ell=int(rng.choice([4, 5, 6])),
+                aniso=float(np.exp(rng.uniform(0.0, np.log(100.0)))), pert=float(rng.uniform(0.0, 0.2)),
+                seed=int(seed))
 
 
-def run_once(sv: V.Solver, dev, b, tau, tol, levels, restart, rtol, maxit) -> RunResult:
+def make_system(r):
+    return synth.upwind_system(r["side"], r["side"], r["side"], ell_choices=(r["ell"],), pe_range=(0.1, 1000.0),
+                               anisotropy=r["aniso"], perturb=r["pert"], seed=r["seed"])
+
+
+def run_once(sv: V.Solver, dev, b, tau, tols, levels=LEVELS, restart=RESTART, rtol=RTOL, maxit=MAXIT) -> RunResult:
+    tols = tuple(float(t) for t in np.broadcast_to(np.asarray(tols, float), (levels + 1,)))
     try:
         sv.compress(*dev, tau)
-        sv.factor(levels, tol)
+        sv.factor(levels, list(tols))
         _, info = sv.solve(b, tol=rtol, restart=restart, maxit=maxit)
     except V.VbarmsError:
-        return RunResult(tau, tol, False, 0, math.inf, math.inf)
+        return RunResult(tau, tols, False, 0, math.inf, math.inf)
     st = sv.stats()
     ok = info.status == 0 and info.true_relres <= rtol
-    return RunResult(tau, tol, ok, info.iters, st.compress_ms + st.factor_ms + st.solve_ms, info.true_relres)
+    return RunResult(tau, tols, ok, info.iters, st.compress_ms + st.factor_ms + st.solve_ms, info.true_relres)
 
 
-def sweep(system, levels=3, restart=50, rtol=1e-8, maxit=400, taus=TAUS, tols=TOLS, repeats=1):
-    """Runs every (tau, t) of the grid on one system; returns (features, [RunResult])."""
+def run_median(sv, dev, b, tau, tols, repeats=3, **kw) -> RunResult:
+    """The run with the median time of `repeats` identical runs (results are deterministic)."""
+    runs = sorted((run_once(sv, dev, b, tau, tols, **kw) for _ in range(repeats)), key=lambda r: r.ms)
+    return runs[len(runs) // 2]
+
+
+def sweep(system, levels=LEVELS, taus=TAUS, tols=TOLS, refine=True):
+    """Runs the (tau, t) grid on one system, then refines the best point level by level.
+
+    Returns (features, grid results, label dict)."""
     import torch
     sv = V.Solver()
     dev = V.csr_to_device(system)
     b = torch.as_tensor(system.b, device="cuda")
     feats = sv.features(*dev)
-    res = []
+    run_once(sv, dev, b, TAUS[-1], TOLS[1], levels)  # warm-up (library caches, clocks)
+    grid = [run_once(sv, dev, b, tau, tol, levels) for tau in taus for tol in tols]
+    ok = [r for r in grid if r.ok]
+    if not ok:
+        sv.close()
+        return feats, grid, None
+    best = min(ok, key=lambda r: r.ms)
+    cur = run_median(sv, dev, b, best.tau, best.tols, levels=levels)
+    if refine:
+        for lvl in range(levels + 1):
+            for f in (0.1, 10.0):
+                t = list(cur.tols)
+                t[lvl] = float(np.clip(t[lvl] * f, 1e-7, 1e-1))
+                if t[lvl] == cur.tols[lvl]:
+                    continue
+                r = run_median(sv, dev, b, cur.tau, t, levels=levels)
+                if r.ok and r.ms < 0.98 * cur.ms:
+                    cur = r
+    sv.close()
+    return feats, grid, dict(tau=cur.tau, tols=list(cur.tols), ms=cur.ms, iters=cur.iters)
+
+
+def target(lab):
+    return np.array([lab["tau"]] + [math.log10(t) for t in lab["tols"]], dtype=np.float32)
+
+
+def best_constant(records, taus=TAUS, tols=TOLS):
+    """The grid setting with the smallest geometric mean, over the training matrices, of its
+    time over that matrix's best grid time (a setting that fails counts as FAIL_RATIO)."""
+    best, best_score = None, math.inf
     for tau in taus:
         for tol in tols:
-            best = None
-            for _ in range(repeats):
-                r = run_once(sv, dev, b, tau, tol, levels, restart, rtol, maxit)
-                best = r if best is None or r.ms < best.ms else best
-            res.append(best)
-    sv.close()
-    return feats, res
-
-
-def label(results, levels):
-    ok = [r for r in results if r.ok]
-    if not ok:
-        tau, tol = DEFAULT_TAU, DEFAULT_TOL
-    else:
-        r = min(ok, key=lambda r: r.ms)
-        tau, tol = r.tau, r.tol
-    return np.array([tau] + [math.log10(tol)] * (levels + 1), dtype=np.float32)
+            logs = []
+            for rec in records:
+                g = {(r[0], r[1]): r for r in rec["grid"]}
+                okt = [r[3] for r in rec["grid"] if r[2]]
+                r = g[(tau, tol)]
+                logs.append(math.log(r[3] / min(okt)) if r[2] else math.log(FAIL_RATIO))
+            score = float(np.mean(logs))
+            if score < best_score:
+                best, best_score = (tau, tol), score
+    return best, math.exp(best_score)
 
 
 class Predictor:
     """Feature normalization + the MLP; predicts (tau, [t_0..t_L])."""
 
-    def __init__(self, levels=3, seed=0):
+    def __init__(self, levels=LEVELS, seed=0):
         self.levels = levels
         self.net = V.Mlp(V.NFEAT, HIDDEN, DEPTH, levels + 2)
         rng = np.random.default_rng(seed)
@@ -110,7 +155,7 @@ class Predictor:
         self.ymu = np.zeros(levels + 2, np.float32)
         self.ysd = np.ones(levels + 2, np.float32)
 
-    def fit(self, X, Y, epochs=400, lr=3e-3, batch=64, seed=0):
+    def fit(self, X, Y, epochs=400, lr=3e-3, batch=32, seed=0):
         X = np.asarray(X, np.float32)
         Y = np.asarray(Y, np.float32)
         self.mu, self.sd = X.mean(0), X.std(0) + 1e-6
@@ -133,6 +178,50 @@ class Predictor:
         out = []
         for row in y:
             tau = float(np.clip(row[0], 0.5, 1.0))
-            tols = [float(10.0 ** np.clip(v, -8.0, -1.0)) for v in row[1:]]
+            tols = [float(10.0 ** np.clip(v, -7.0, -1.0)) for v in row[1:]]
             out.append((tau, tols))
         return out
+
+
+def build_dataset(count, out, side_range=(20, 34), first_seed=0):
+    """Labels `count` training matrices and writes them as JSON (one record per matrix)."""
+    recs = []
+    t0 = time.time()
+    for k in range(first_seed, first_seed + count):
+        r = recipe(k, side_range)
+        s = make_system(r)
+        feats, grid, lab = sweep(s)
+        rec = dict(recipe=r, n=s.n, nnz=s.nnz, features=[float(x) for x in feats],
+                   grid=[[g.tau, g.tols[0], bool(g.ok), g.ms if g.ok else None, g.iters] for g in grid], label=lab)
+        recs.append(rec)
+        print(f"[learned] {k}: n={s.n} side={r['side']} ell={r['ell']} pert={r['pert']:.3f} aniso={r['aniso']:.1f} "
+              f"label={lab} ({time.time() - t0:.0f} s)", flush=True)
+        with open(out, "w") as f:
+            json.dump(dict(levels=LEVELS, taus=TAUS, tols=TOLS, restart=RESTART, rtol=RTOL, maxit=MAXIT,
+                           records=recs), f)
+    return recs
+
+
+def load_dataset(path):
+    with open(path) as f:
+        d = json.load(f)
+    recs = [r for r in d["records"] if r["label"] is not None]
+    for r in recs:
+        for g in r["grid"]:
+            if g[3] is None:
+                g[3] = math.inf
+    return d, recs
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="label the training matrices of the learned parameter selection")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--count", type=int, default=100)
+    ap.add_argument("--first-seed", type=int, default=0)
+    a = ap.parse_args(argv)
+    build_dataset(a.count, a.out, first_seed=a.first_seed)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -127,6 +127,102 @@ def _comparators(wl, side, V, torch):
     return 0
 
 
+def _batch_systems(count, seed=4):
+    """The batched workload: `count` systems of the 40^3 recipe (14-neighbour stencil, 10%
+    block perturbation) with n log-uniform in [5k, 200k] and ell in {3, 5, 6}; each grid is
+    as close to a cube as the node count allows."""
+    import numpy as np
+    from paper_1508_02219_amd import synth
+
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        n = float(np.exp(rng.uniform(np.log(5e3), np.log(2e5))))
+        ell = int(rng.choice([3, 5, 6]))
+        nodes = max(8, int(round(n / ell)))
+        nx = max(2, int(round(nodes ** (1.0 / 3.0))))
+        ny = max(2, int(round((nodes / nx) ** 0.5)))
+        nz = max(2, int(round(nodes / (nx * ny))))
+        out.append(synth.grid_system(nx, ny, nz, ell, "14rand", 0.10, seed=1000 + q))
+    return out
+
+
+def _batch_bench(args, V, torch):
+    """Batched uneven systems: all systems compressed, factored and solved for every
+    right-hand side through shared launches, against one-at-a-time solves on a sample."""
+    import numpy as np
+
+    count, nrhs, tau, levels, droptol, restart = args.batch, 16, 0.8, 3, 1e-4, 50
+    t0 = time.perf_counter()
+    systems = _batch_systems(count)
+    print(f"[bench] generated {count} systems (n = {sum(s.n for s in systems)}) in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    devs = [V.csr_to_device(s) for s in systems]
+    N = sum(s.n for s in systems)
+    rng = np.random.default_rng(16)
+    B = torch.as_tensor(rng.standard_normal((nrhs, N)), device="cuda")
+    bs = V.BatchSolver()
+
+    def batched():
+        bs.factor(devs, tau, levels, droptol)
+        X, info = bs.solve(B, tol=TOL, restart=restart, maxit=MAXIT)
+        return info
+
+    for w in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        info = batched()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.steps
+    ok = all(i.status == 0 and i.true_relres <= TOL for row in info for i in row)
+    its = [i.iters for row in info for i in row]
+    fs = bs.handle().stats()
+    bs.close()
+    # one at a time: every 16th system, each compressed, factored and solved for its 16
+    # right-hand sides on its own handle; scaled to the whole batch by the unknowns
+    sample = list(range(0, count, max(1, count // 16)))
+    sv = V.Solver()
+    off = np.concatenate([[0], np.cumsum([s.n for s in systems])])
+    for q in sample[:1]:  # warm-up
+        sv.compress(*devs[q], tau)
+        sv.factor(levels, droptol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_sample = 0
+    for q in sample:
+        sv.compress(*devs[q], tau)
+        sv.factor(levels, droptol)
+        for r in range(nrhs):
+            x, inf = sv.solve(B[r, off[q]:off[q + 1]].contiguous(), tol=TOL, restart=restart, maxit=MAXIT)
+            ok = ok and inf.status == 0
+        n_sample += systems[q].n
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) * N / n_sample
+    sv.close()
+    solves = count * nrhs
+    out = {"metric": "aggregate solves/s, batched vs one-at-a-time", "value": round(solves / tb, 3),
+           "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1000.0 * tb, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{count} systems of the 40^3 recipe, n log-uniform in [5k, 200k], ell in "
+                                  f"{{3, 5, 6}}, {nrhs} N(0,1) right-hand sides each", "systems": count,
+                      "n_total": N, "nnz_total": int(sum(s.nnz for s in systems)), "tau": tau, "levels": levels,
+                      "droptol": droptol, "krylov": f"FGMRES({restart})", "tol": TOL},
+           "all_converged": bool(ok), "iters_min_median_max": [int(min(its)), int(np.median(its)), int(max(its))],
+           "batched_s": round(tb, 4), "batched_phases_ms": {"compress": round(fs.compress_ms, 2),
+                                                            "factor": round(fs.factor_ms, 2),
+                                                            "solve_all_rhs": round(fs.solve_ms, 2)},
+           "one_at_a_time_s": round(ts, 3), "one_at_a_time_solves_per_s": round(solves / ts, 3),
+           "one_at_a_time_sample": f"{len(sample)} of {count} systems ({n_sample} unknowns), each compressed, "
+                                   f"factored and solved for its {nrhs} right-hand sides on its own handle; time "
+                                   f"scaled by total/sample unknowns",
+           "batched_speedup": round(ts / tb, 3)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +233,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device-to-device copies (the reference for counter scaling)")
+    ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
+                    help="instead of the benchmark, time COUNT uneven systems with 16 right-hand sides each, "
+                         "batched and one at a time")
     ap.add_argument("--comparators", type=int, default=0, metavar="SIDE",
                     help="instead of the benchmark, compare VBARMS with block ILUT alone (VBILUT, levels = 0) and "
                          "with pointwise ILUT (1x1 blocks, levels = 0) on a SIDE^3 grid of the workload's recipe")
@@ -163,6 +262,8 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}), flush=True)
         return 0
+    if args.batch:
+        return _batch_bench(args, V, torch)
     wl = WORKLOADS[args.workload]
     tau, levels, droptol, restart = wl["tau"], wl["levels"], wl["droptol"], wl["restart"]
     if args.comparators:

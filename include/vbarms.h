@@ -204,6 +204,40 @@ int vbarms_solve(vbarms_t h, const double *b, double *x, double tol, int32_t res
  * [0, 1]). */
 int vbarms_set_fp64_fallback(vbarms_t h, int32_t enable, int32_t f32_iter_limit, double min_pivot_ratio);
 
+/* ---------------------------------------------------------------------------------- */
+/* Batches of independent systems (not part of the paper's method: a way to run many     */
+/* systems of different sizes through the same launches).                               */
+/* ---------------------------------------------------------------------------------- */
+/* The systems are assembled into one block-diagonal matrix, which is compressed and
+ * factored like a single system: rows of different systems share no column, so no block,
+ * independent-set decision, Schur update or ILUT row couples two systems, and every system
+ * gets exactly the factors it would get alone, while every launch covers all systems.  The
+ * solves run FGMRES for every system in lockstep (shared launches, per-system inner
+ * products, Hessenberg matrices, convergence and restarts). */
+typedef struct vbarms_batch_ctx *vbarms_batch_t;
+int vbarms_batch_create(vbarms_batch_t *b, void *hip_stream);
+int vbarms_batch_destroy(vbarms_batch_t b);
+const char *vbarms_batch_last_error(vbarms_batch_t b);
+/* The handle of the combined system (owned by the batch): statistics, timing and the
+ * factor exports work on it; its numbering is the concatenation of the systems. */
+vbarms_t vbarms_batch_handle(vbarms_batch_t b);
+/* systems: HOST array of nsys descriptors whose arrays are DEVICE pointers (as in
+ * vbarms_compress; copied, the caller may free them afterwards).  tau and p as in
+ * vbarms_compress and vbarms_factor.  Errors: ARG (nsys < 1, more than 2^31 - 1 rows in
+ * total), and those of vbarms_compress and vbarms_factor. */
+int vbarms_batch_factor(vbarms_batch_t b, int32_t nsys, const vbarms_csr *systems, double tau,
+                        const vbarms_fparams *p);
+/* off[nsys+1] (HOST): first row of every system in the concatenated numbering. */
+int vbarms_batch_offsets(vbarms_batch_t b, int64_t *off);
+/* Solves A_s x = b for every system s and every right-hand side r < nrhs.  B, X: DEVICE,
+ * nrhs columns of length N = total rows, column r at B + r N, system s's rows at
+ * [off_s, off_{s+1}) of a column; X holds the initial guesses on entry.  Per system and
+ * column: stops at a true relative residual <= tol or after maxit Arnoldi steps.
+ * info (HOST, may be NULL): nrhs * nsys entries, column r's system s at r * nsys + s.
+ * Returns VBARMS_NOT_CONVERGED if any system missed tol. */
+int vbarms_batch_solve(vbarms_batch_t b, const double *B, double *X, int32_t nrhs, double tol, int32_t restart,
+                       int32_t maxit, vbarms_sinfo *info);
+
 /* Timings and sizes of the last compress / factor / solve on this handle (HOST). */
 int vbarms_get_stats(vbarms_t h, vbarms_fstats *st);
 

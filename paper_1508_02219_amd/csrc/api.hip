@@ -340,6 +340,51 @@ void need_factors(vbarms_t h) {
 
 }  // namespace
 
+// Several independent systems held as one block-diagonal system (vbarms_batch_*).
+struct vbarms_batch_ctx {
+    vbarms_t h = nullptr;          // handle of the combined system
+    std::vector<int64_t> off;      // first row of every system in the combined numbering
+    Segments seg;
+    BatchKrylovWork kw;
+    std::string last_error;
+    bool have_factors = false;
+};
+
+namespace {
+
+// rows [off_s, off_s + n_s) of the combined CSR from system s: column indices shifted by
+// off_s, row offsets by the entries of the systems before it
+__global__ void k_batch_rows(int n, const int64_t *rp, int64_t row0, int64_t nnz0, int64_t *crp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) crp[row0 + i] = nnz0 + rp[i];
+}
+__global__ void k_batch_cols(int64_t nnz, const int *ci, int col0, int *cci) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) cci[k] = ci[k] + col0;
+}
+
+template <class F>
+int batch_guarded(vbarms_batch_t b, F &&body) {
+    if (!b) return VBARMS_ERR_ARG;
+    StreamScope scope(b->h->stream);
+    try {
+        b->last_error.clear();
+        VB_HIP(hipSetDevice(b->h->device));
+        return body();
+    } catch (const VbError &e) {
+        b->last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        b->last_error = "host allocation failed";
+        return VBARMS_ERR_OOM;
+    } catch (...) {
+        b->last_error = "unexpected internal error";
+        return VBARMS_ERR_HIP;
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 int vbarms_create(vbarms_t *out, void *hip_stream) {
@@ -569,6 +614,123 @@ int vbarms_set_fp64_fallback(vbarms_t h, int32_t enable, int32_t f32_iter_limit,
         h->fb_iter_limit = f32_iter_limit;
         h->fb_min_ratio = min_pivot_ratio;
         return VBARMS_OK;
+    });
+}
+
+int vbarms_batch_create(vbarms_batch_t *out, void *hip_stream) {
+    if (!out) return VBARMS_ERR_ARG;
+    *out = nullptr;
+    vbarms_batch_ctx *b = new (std::nothrow) vbarms_batch_ctx();
+    if (!b) return VBARMS_ERR_OOM;
+    int rc = vbarms_create(&b->h, hip_stream);
+    if (rc != VBARMS_OK) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return VBARMS_OK;
+}
+
+int vbarms_batch_destroy(vbarms_batch_t b) {
+    if (!b) return VBARMS_ERR_ARG;
+    vbarms_t h = b->h;
+    {
+        StreamScope scope(h->stream);  // buffers are released in stream order
+        (void)hipSetDevice(h->device);
+        b->seg = Segments();
+        b->kw = BatchKrylovWork();
+    }
+    delete b;
+    return vbarms_destroy(h);
+}
+
+const char *vbarms_batch_last_error(vbarms_batch_t b) { return b ? b->last_error.c_str() : "invalid handle"; }
+
+vbarms_t vbarms_batch_handle(vbarms_batch_t b) { return b ? b->h : nullptr; }
+
+int vbarms_batch_factor(vbarms_batch_t b, int32_t nsys, const vbarms_csr *systems, double tau,
+                        const vbarms_fparams *p) {
+    return batch_guarded(b, [&] {
+        if (nsys < 1 || !systems || !p) fail(VBARMS_ERR_ARG, "invalid batch");
+        vbarms_t h = b->h;
+        hipStream_t s = h->stream;
+        b->have_factors = false;
+        std::vector<int64_t> off(nsys + 1, 0), noff(nsys + 1, 0);
+        for (int q = 0; q < nsys; ++q) {
+            validate_csr(&systems[q]);
+            off[q + 1] = off[q] + systems[q].n;
+            noff[q + 1] = noff[q] + systems[q].nnz;
+        }
+        if (off[nsys] > INT32_MAX) fail(VBARMS_ERR_ARG, "the systems hold more than 2^31 - 1 rows together");
+        const int ntot = (int)off[nsys];
+        // the block-diagonal matrix of all systems, assembled on the device
+        DBuf<int64_t> crp(ntot + 1);
+        DBuf<int> cci(std::max<int64_t>(noff[nsys], 1));
+        DBuf<double> cva(std::max<int64_t>(noff[nsys], 1));
+        for (int q = 0; q < nsys; ++q) {
+            const vbarms_csr &A = systems[q];
+            if (A.n > 0) {
+                k_batch_rows<<<grid_for(A.n, 256), 256, 0, s>>>(A.n, A.rowptr, off[q], noff[q], crp.p);
+                VB_LAUNCH_CHECK();
+            }
+            if (A.nnz > 0) {
+                k_batch_cols<<<grid_for(A.nnz, 256), 256, 0, s>>>(A.nnz, A.col, (int)off[q], cci.p + noff[q]);
+                VB_LAUNCH_CHECK();
+                VB_HIP(hipMemcpyAsync(cva.p + noff[q], A.val, sizeof(double) * A.nnz, hipMemcpyDeviceToDevice, s));
+            }
+        }
+        to_device(crp.p + ntot, &noff[nsys], 1, s);
+        VB_HIP(hipStreamSynchronize(s));  // noff is a copy source
+        vbarms_csr C{ntot, noff[nsys], crp.p, cci.p, cva.p};
+        int rc = vbarms_compress(h, &C, tau, nullptr, nullptr, nullptr);
+        if (rc != VBARMS_OK) fail(rc, std::string("batch compress: ") + h->last_error);
+        // Rows of different systems share no column, so no block spans two systems, and
+        // blocks follow their smallest row: every system keeps its row range in the
+        // compressed numbering.
+        b->off = off;
+        b->seg.build(off, s);
+        rc = vbarms_factor(h, p);
+        if (rc != VBARMS_OK) fail(rc, std::string("batch factor: ") + h->last_error);
+        b->have_factors = true;
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_batch_offsets(vbarms_batch_t b, int64_t *off) {
+    if (!b || !off) return VBARMS_ERR_ARG;
+    std::copy(b->off.begin(), b->off.end(), off);
+    return VBARMS_OK;
+}
+
+int vbarms_batch_solve(vbarms_batch_t b, const double *B, double *X, int32_t nrhs, double tol, int32_t restart,
+                       int32_t maxit, vbarms_sinfo *info) {
+    return batch_guarded(b, [&] {
+        if (!b->have_factors) fail(VBARMS_ERR_STATE, "no factorization: call vbarms_batch_factor first");
+        if (nrhs < 1 || restart < 1 || maxit < 0 || !(tol >= 0.0) || !B || !X)
+            fail(VBARMS_ERR_ARG, "invalid solver parameters");
+        vbarms_t h = b->h;
+        hipStream_t s = h->stream;
+        Timer tm(s);
+        const int64_t n = b->off.back();
+        const int ns = b->seg.nseg;
+        DBuf<double> bc(std::max<int64_t>(n, 1)), xc(std::max<int64_t>(n, 1));
+        auto pre = [&](const double *in, double *out) { precond_apply(h, in, out); };
+        std::vector<vbarms_sinfo> inf;
+        int worst = VBARMS_OK;
+        for (int r = 0; r < nrhs; ++r) {
+            h->err.reset(s);
+            gather_perm((int)n, h->perm.p, B + (int64_t)r * n, bc.p, s);
+            gather_perm((int)n, h->perm.p, X + (int64_t)r * n, xc.p, s);
+            const int st = fgmres_batch_run(h->A, b->kw, b->seg, bc.p, xc.p, tol, restart, maxit, pre, inf, s);
+            check_dev_err(h, "batch solve");
+            scatter_perm((int)n, h->perm.p, xc.p, X + (int64_t)r * n, s);
+            if (st != VBARMS_OK) worst = VBARMS_NOT_CONVERGED;
+            if (info)
+                for (int q = 0; q < ns; ++q) info[(int64_t)r * ns + q] = inf[q];
+        }
+        VB_HIP(hipStreamSynchronize(s));
+        h->stats.solve_ms = tm.stop();
+        return worst;
     });
 }
 

@@ -138,6 +138,29 @@ struct KrylovWork {
 };
 int fgmres_run(const Panel<double> &A, KrylovWork &kw, const double *b, double *x, double tol, int m, int maxit,
                const std::function<void(const double *, double *)> &precond, vbarms_sinfo *info, hipStream_t s);
+
+// Consecutive row ranges of independent systems inside one combined numbering, with the
+// chunking used by the per-system dot products (batch.hip).
+struct Segments {
+    int nseg = 0, nchunk = 0;
+    std::vector<int64_t> off;          // [nseg+1]
+    DBuf<int64_t> d_off, d_cbeg, d_cend;
+    DBuf<int> d_segchunk;              // [nseg+1] first chunk of every segment
+    DBuf<int> rowseg;                  // [n] segment of every row
+    void build(const std::vector<int64_t> &offsets, hipStream_t s);
+};
+struct BatchKrylovWork {
+    DBuf<double> V, Z, partial, hbuf, ybuf;
+    DBuf<int> ibuf;
+    int64_t n = 0;
+    int m = 0, nseg = 0, nchunk = 0;
+    void ensure(int64_t n_, int m_, int nseg_, int nchunk_);
+};
+// FGMRES(m) on every segment of A (block diagonal over the segments) in lockstep; info[s]
+// per system.  Returns VBARMS_OK when every system converged.
+int fgmres_batch_run(const Panel<double> &A, BatchKrylovWork &kw, const Segments &sg, const double *b, double *x,
+                     double tol, int m, int maxit, const std::function<void(const double *, double *)> &precond,
+                     std::vector<vbarms_sinfo> &info, hipStream_t s);
 void gather_perm(int n, const int *perm, const double *src, double *dst, hipStream_t s);
 // VBARMS_NFEAT features of a CSR matrix (host output)
 void matrix_features(int n, int64_t nnz, const int64_t *rowptr, const int *col, const double *val, float *f,

@@ -111,7 +111,9 @@ def _node_links(nx: int, ny: int, nz: int, stencil: str, seed: int):
 
 
 def _csr_from_coo(n, rows, cols, vals):
-    o = np.lexsort((cols, rows))
+    # row-major order of the entries (a stable sort on one key: the same order as sorting
+    # by row, then column, then position)
+    o = np.argsort(np.asarray(rows, np.int64) * np.int64(n) + np.asarray(cols, np.int64), kind="stable")
     rows, cols, vals = rows[o], cols[o], vals[o]
     rowptr = np.zeros(n + 1, dtype=np.int64)
     np.add.at(rowptr, rows + 1, 1)

@@ -87,6 +87,13 @@ SIGNATURES = {
     "vbarms_spmv_noalloc": (C.c_int, [_P, _P, _P]),
     "vbarms_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, C.c_int32, C.POINTER(SInfo)]),
     "vbarms_get_stats": (C.c_int, [_P, C.POINTER(FStats)]),
+    "vbarms_batch_create": (C.c_int, [C.POINTER(C.c_void_p), _P]),
+    "vbarms_batch_destroy": (C.c_int, [_P]),
+    "vbarms_batch_last_error": (C.c_char_p, [_P]),
+    "vbarms_batch_handle": (C.c_void_p, [_P]),
+    "vbarms_batch_factor": (C.c_int, [_P, C.c_int32, _P, C.c_double, C.POINTER(_FParams)]),
+    "vbarms_batch_offsets": (C.c_int, [_P, _P]),
+    "vbarms_batch_solve": (C.c_int, [_P, _P, _P, C.c_int32, C.c_double, C.c_int32, C.c_int32, _P]),
     "vbarms_set_fp64_fallback": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double]),
     "vbarms_device_memory": (C.c_int, [_P]),
     "vbarms_set_graphs": (C.c_int, [_P, C.c_int32]),
@@ -186,9 +193,9 @@ class Solver:
         self._A = None
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and not getattr(self, "_borrowed", False):
             lib().vbarms_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -348,6 +355,93 @@ class Solver:
         if piv is not None:
             piv = piv[: rb[-1]]
         return Exported(rb, cb, rowptr, colidx[:nb], vals[:nv], piv)
+
+
+def _fparams(levels, droptol, drop_schur=1, precision=F64, is_order=IS_NATURAL):
+    p = _FParams()
+    p.levels = levels
+    dt = np.asarray(droptol, dtype=np.float64).ravel()
+    if dt.size == 1:
+        dt = np.full(levels + 1, dt[0])
+    for i in range(levels + 1):
+        p.droptol[i] = float(dt[i])
+    p.drop_schur = drop_schur
+    p.is_order = is_order
+    p.precision = precision
+    return p
+
+
+class BatchSolver:
+    """Several independent systems factored and solved through shared launches."""
+
+    def __init__(self, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("VBARMS needs a ROCm GPU")
+        self._torch = torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        b = C.c_void_p()
+        rc = lib().vbarms_batch_create(C.byref(b), C.c_void_p(s.cuda_stream))
+        if rc != OK:
+            raise VbarmsError(rc, "vbarms_batch_create failed")
+        self.b = b
+        self.off = None
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().vbarms_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow_not_converged=False):
+        if rc == OK or (allow_not_converged and rc == NOT_CONVERGED):
+            return rc
+        msg = lib().vbarms_batch_last_error(self.b)
+        raise VbarmsError(rc, msg.decode() if msg else "")
+
+    def factor(self, systems, tau, levels, droptol, drop_schur=1, precision=F64, is_order=IS_NATURAL):
+        """systems: list of (rowptr, col, val) device tensors."""
+        torch = self._torch
+        descs = (_Csr * len(systems))()
+        self._keep = systems
+        for q, (rp, ci, va) in enumerate(systems):
+            descs[q] = _Csr(rp.numel() - 1, int(ci.numel()), _dev_ptr(rp, torch.int64), _dev_ptr(ci, torch.int32),
+                            _dev_ptr(va, torch.float64))
+        p = _fparams(levels, droptol, drop_schur, precision, is_order)
+        self._check(lib().vbarms_batch_factor(self.b, len(systems), descs, float(tau), C.byref(p)))
+        off = np.zeros(len(systems) + 1, np.int64)
+        self._check(lib().vbarms_batch_offsets(self.b, _np_ptr(off)))
+        self.off = off
+        return off
+
+    def solve(self, B, X0=None, tol=1e-8, restart=30, maxit=1000):
+        """B: device tensor [nrhs, N] (row r = right-hand side r of every system); returns
+        (X, info) with info[r][s] the solver info of system s for right-hand side r."""
+        torch = self._torch
+        B = B.contiguous()
+        nrhs = B.shape[0]
+        X = torch.zeros_like(B) if X0 is None else X0.clone().contiguous()
+        ns = len(self.off) - 1 if self.off is not None else 0
+        info = (SInfo * max(1, nrhs * ns))()
+        rc = lib().vbarms_batch_solve(self.b, _dev_ptr(B, torch.float64), _dev_ptr(X, torch.float64), nrhs,
+                                      float(tol), int(restart), int(maxit), info)
+        self._check(rc, allow_not_converged=True)
+        return X, [[info[r * ns + q] for q in range(ns)] for r in range(nrhs)]
+
+    def handle(self):
+        """A Solver view of the combined system (apply, spmv, stats, exports); not owned."""
+        sv = Solver.__new__(Solver)
+        sv._torch = self._torch
+        sv.h = C.c_void_p(lib().vbarms_batch_handle(self.b))
+        sv.n = int(self.off[-1])
+        sv._A = None
+        sv._borrowed = True
+        return sv
 
 
 class Mlp:

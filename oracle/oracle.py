@@ -43,6 +43,8 @@ def lib():
         i32, i64, dbl = C.c_int32, C.c_int64, C.c_double
         l.orc_compress.argtypes = [C.c_int, P, P, dbl, P, P, P]
         l.orc_compress.restype = C.c_int
+        l.orc_graph_compress.argtypes = [C.c_int, P, P, dbl, P, P, P]
+        l.orc_graph_compress.restype = C.c_int
         l.orc_build.argtypes = [C.c_int, P, P, P, P, P, C.c_int, C.c_int, P, C.c_int, C.c_int]
         l.orc_build.restype = P
         l.orc_free.argtypes = [P]
@@ -87,6 +89,18 @@ def compress(n, rowptr, col, tau):
     st = lib().orc_compress(n, _p(rp), _p(ci), float(tau), _p(perm), _p(bptr), _p(p))
     if st != OK:
         raise ValueError(f"orc_compress failed ({st})")
+    return perm[:n].copy(), bptr[: p[0] + 1].copy()
+
+
+def graph_compress(n, rowptr, col, mu):
+    """Graph-based compression with target density mu (Sec. 2.2, Alg. 1). Returns (perm, bptr)."""
+    rp, ci, _ = _csr(rowptr, col)
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    bptr = np.zeros(n + 1, dtype=np.int32)
+    p = np.zeros(1, dtype=np.int32)
+    st = lib().orc_graph_compress(n, _p(rp), _p(ci), float(mu), _p(perm), _p(bptr), _p(p))
+    if st != OK:
+        raise ValueError(f"orc_graph_compress failed ({st})")
     return perm[:n].copy(), bptr[: p[0] + 1].copy()
 
 

@@ -283,6 +283,161 @@ int orc_compress(int n, const int64_t *rowptr, const int32_t *col, double tau,
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Graph-based compression (Sec. 2.2, Alg. 1; readings G1-G4)                */
+/* ------------------------------------------------------------------------- */
+/* G1 supernodes start as the classes of rows with identical patterns (the checksum step);
+ * G2 a supernode X (visited in ascending order of its smallest row) tries, in ascending
+ *    order of their smallest rows, the supernodes adjacent to it in the quotient graph of
+ *    A + A^T when its visit starts; a supernode already merged away is skipped, and so is a
+ *    merge that would give more than 32 rows (the largest block of the GPU library);
+ * G3 the merge is kept iff the average block density of the whole ordering after it, nnz(A)
+ *    over the elements of all blocks that hold an entry or lie on the diagonal, is still
+ *    at least mu, tested as nnz >= mu * elements in FP64;
+ * G4 blocks are ordered by their smallest row, rows ascending within a block. */
+#define ORC_GRAPH_MAX_BLOCK 32
+
+/* lexicographic comparison of two row patterns (both sorted ascending) */
+static const int64_t *g_rp;
+static const int32_t *g_ci;
+static int cmp_rows(const void *x, const void *y) {
+    int a = *(const int *)x, b = *(const int *)y;
+    int64_t la = g_rp[a + 1] - g_rp[a], lb = g_rp[b + 1] - g_rp[b];
+    int64_t l = la < lb ? la : lb;
+    for (int64_t k = 0; k < l; ++k) {
+        int ca = g_ci[g_rp[a] + k], cb = g_ci[g_rp[b] + k];
+        if (ca != cb) return (ca > cb) - (ca < cb);
+    }
+    if (la != lb) return (la > lb) - (la < lb);
+    return (a > b) - (a < b);
+}
+
+/* elements of all blocks that hold an entry or lie on the diagonal, for supernode labels
+ * g (any labels; sz[label] = rows) -- straight from the definition */
+static int64_t graph_block_elements(int n, const int64_t *rowptr, const int32_t *col, const int32_t *g,
+                                    const int32_t *sz, int32_t *stamp, int32_t *rows_of, int64_t *rstart) {
+    /* rows of every label */
+    for (int l = 0; l <= n; ++l) rstart[l] = 0;
+    for (int i = 0; i < n; ++i) rstart[g[i] + 1]++;
+    for (int l = 0; l < n; ++l) rstart[l + 1] += rstart[l];
+    int64_t *fill = xmalloc(sizeof(int64_t) * ((size_t)n + 1));
+    memcpy(fill, rstart, sizeof(int64_t) * ((size_t)n + 1));
+    for (int i = 0; i < n; ++i) rows_of[fill[g[i]]++] = i;
+    free(fill);
+    for (int l = 0; l < n; ++l) stamp[l] = -1;
+    int64_t elems = 0;
+    for (int I = 0; I < n; ++I) {
+        if (rstart[I] == rstart[I + 1]) continue;
+        /* the diagonal block always counts */
+        stamp[I] = I;
+        elems += (int64_t)sz[I] * sz[I];
+        for (int64_t t = rstart[I]; t < rstart[I + 1]; ++t) {
+            int i = rows_of[t];
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                int J = g[col[k]];
+                if (stamp[J] != I) {
+                    stamp[J] = I;
+                    elems += (int64_t)sz[I] * sz[J];
+                }
+            }
+        }
+    }
+    return elems;
+}
+
+int orc_graph_compress(int n, const int64_t *rowptr, const int32_t *col, double mu,
+                       int32_t *perm, int32_t *bptr, int32_t *p_out) {
+    if (n < 0 || !(mu > 0.0) || !(mu <= 1.0)) return ORC_ERR_ARG;
+    int64_t nnz = rowptr[n];
+    for (int64_t k = 0; k < nnz; ++k)
+        if (col[k] < 0 || col[k] >= n) return ORC_ERR_ARG;
+    /* G1: identical patterns (sort rows by pattern, equal neighbours join) */
+    int32_t *order = xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    for (int i = 0; i < n; ++i) order[i] = i;
+    g_rp = rowptr; g_ci = col;
+    qsort(order, (size_t)n, sizeof(int32_t), cmp_rows);
+    int32_t *g = xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    for (int t = 0; t < n; ++t) {
+        int i = order[t];
+        g[i] = i;
+        if (t > 0) {
+            int j = order[t - 1];
+            int64_t li = rowptr[i + 1] - rowptr[i], lj = rowptr[j + 1] - rowptr[j];
+            if (li > 0 && li == lj && memcmp(col + rowptr[i], col + rowptr[j], sizeof(int32_t) * li) == 0)
+                g[i] = g[j] < i ? g[j] : i;
+        }
+    }
+    /* labels = smallest row of the class (the sort put equal patterns next to each other
+     * in ascending row order, so g[j] of the first of a run is its smallest row) */
+    int32_t *sz = xcalloc((size_t)n + 1, sizeof(int32_t));
+    for (int i = 0; i < n; ++i) sz[g[i]]++;
+    /* A + A^T adjacency of rows */
+    int64_t *ap = xcalloc((size_t)n + 1, sizeof(int64_t));
+    for (int i = 0; i < n; ++i)
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) { ap[i + 1]++; ap[col[k] + 1]++; }
+    for (int i = 0; i < n; ++i) ap[i + 1] += ap[i];
+    int32_t *adj = xmalloc(sizeof(int32_t) * (size_t)(2 * nnz + 1));
+    int64_t *af = xmalloc(sizeof(int64_t) * ((size_t)n + 1));
+    memcpy(af, ap, sizeof(int64_t) * ((size_t)n + 1));
+    for (int i = 0; i < n; ++i)
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) { adj[af[i]++] = col[k]; adj[af[col[k]]++] = i; }
+    free(af);
+    int32_t *stamp = xmalloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *rows_of = xmalloc(sizeof(int32_t) * ((size_t)n + 1));
+    int64_t *rstart = xmalloc(sizeof(int64_t) * ((size_t)n + 2));
+    int32_t *cand = xmalloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *mark = xmalloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *gtry = xmalloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *first = xmalloc(sizeof(int32_t) * ((size_t)n + 1)); /* smallest row of every label */
+    for (int l = 0; l < n; ++l) { mark[l] = -1; first[l] = l; }
+    /* G2/G3: visit supernodes in ascending order of their smallest row */
+    for (int X = 0; X < n; ++X) {
+        if (g[X] != X || sz[X] == 0) continue; /* not a label, or merged away */
+        int nc = 0;
+        for (int i = 0; i < n; ++i) {
+            if (g[i] != X) continue;
+            for (int64_t k = ap[i]; k < ap[i + 1]; ++k) {
+                int Z = g[adj[k]];
+                if (Z != X && mark[Z] != X) { mark[Z] = X; cand[nc++] = Z; }
+            }
+        }
+        /* ascending smallest row (labels keep their smallest row in first[]) */
+        for (int a = 1; a < nc; ++a) {
+            int v = cand[a], b = a - 1;
+            while (b >= 0 && first[cand[b]] > first[v]) { cand[b + 1] = cand[b]; --b; }
+            cand[b + 1] = v;
+        }
+        for (int c = 0; c < nc; ++c) {
+            int Z = cand[c];
+            if (sz[Z] == 0) continue;                              /* merged away meanwhile */
+            if (sz[X] + sz[Z] > ORC_GRAPH_MAX_BLOCK) continue;
+            for (int i = 0; i < n; ++i) gtry[i] = g[i] == Z ? X : g[i];
+            int32_t sx = sz[X], szz = sz[Z];
+            sz[X] = sx + szz; sz[Z] = 0;
+            int64_t el = graph_block_elements(n, rowptr, col, gtry, sz, stamp, rows_of, rstart);
+            if ((double)nnz >= mu * (double)el) {
+                memcpy(g, gtry, sizeof(int32_t) * (size_t)n);
+                if (first[Z] < first[X]) first[X] = first[Z];
+            } else {
+                sz[X] = sx; sz[Z] = szz;
+            }
+        }
+    }
+    /* G4: blocks by smallest row, rows ascending */
+    int p = 0;
+    for (int l = 0; l < n; ++l) mark[l] = -1;
+    for (int i = 0; i < n; ++i) if (mark[g[i]] < 0) mark[g[i]] = p++;   /* rank by smallest row */
+    int64_t *bs = xcalloc((size_t)p + 1, sizeof(int64_t));
+    for (int i = 0; i < n; ++i) bs[mark[g[i]] + 1]++;
+    for (int b = 0; b < p; ++b) bs[b + 1] += bs[b];
+    for (int b = 0; b <= p; ++b) bptr[b] = (int32_t)bs[b];
+    for (int i = 0; i < n; ++i) perm[bs[mark[g[i]]]++] = i;
+    *p_out = p;
+    free(order); free(g); free(sz); free(ap); free(adj); free(stamp); free(rows_of); free(rstart);
+    free(cand); free(mark); free(gtry); free(first); free(bs);
+    return ORC_OK;
+}
+
 /* Permuted block matrix P_B A P_B^T (Eq. blockperm): block (I,J) exists iff an entry of
  * A falls in it; the diagonal block always exists (R6); missing entries are zero. */
 static void build_vbcsr(int n, const int64_t *rowptr, const int32_t *col, const double *val,

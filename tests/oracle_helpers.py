@@ -166,3 +166,58 @@ def dense_block_ilut(a, rb, t):
             if r >= 1.0:
                 U[(i, j)] = wj.copy()
     return L, U, D, mult_ratios, u_ratios
+
+
+def graph_compress_bruteforce(n, rowptr, col, mu, max_block=32):
+    """Greedy merging of supernodes (Sec. 2.2, Alg. 1) written with Python sets: start from the
+    identical-pattern classes; for every supernode in ascending smallest row, try its
+    quotient-graph neighbours (A + A^T) in ascending smallest row and keep a merge when the
+    average block density of the whole ordering stays >= mu.  Returns (perm, bptr,
+    closest_margin), the margin being the smallest |nnz - mu * elements| / nnz seen."""
+    pats = [tuple(col[rowptr[i]:rowptr[i + 1]].tolist()) for i in range(n)]
+    first = {}
+    label = [first.setdefault(pats[i], i) for i in range(n)]
+    members = {}
+    for i in range(n):
+        members.setdefault(label[i], set()).add(i)
+    entries = [(i, int(j)) for i in range(n) for j in col[rowptr[i]:rowptr[i + 1]]]
+    nnz = len(entries)
+    nbr = [set() for _ in range(n)]
+    for i, j in entries:
+        nbr[i].add(j)
+        nbr[j].add(i)
+
+    def elements(lab, mem):
+        blocks = {(lab[i], lab[j]) for i, j in entries} | {(s, s) for s in mem}
+        return sum(len(mem[a]) * len(mem[b]) for a, b in blocks)
+
+    margin = float("inf")
+    for X in sorted(members):
+        if X not in members:
+            continue
+        cand = sorted({label[j] for i in members[X] for j in nbr[i]} - {X}, key=lambda s: min(members[s]))
+        for Z in cand:
+            if Z not in members or len(members[X]) + len(members[Z]) > max_block:
+                continue
+            lab2 = [X if label[i] == Z else label[i] for i in range(n)]
+            mem2 = {k: v for k, v in members.items() if k != Z}
+            mem2[X] = members[X] | members[Z]
+            el = elements(lab2, mem2)
+            margin = min(margin, abs(nnz - mu * el) / nnz)
+            if nnz >= mu * el:
+                label, members = lab2, mem2
+    blocks = sorted(members.values(), key=min)
+    perm = [i for b in blocks for i in sorted(b)]
+    bptr = np.concatenate([[0], np.cumsum([len(b) for b in blocks])])
+    return np.array(perm, np.int32), bptr.astype(np.int32), margin
+
+
+def average_block_density(n, rowptr, col, perm, bptr):
+    """nnz / elements of the blocks holding an entry or on the diagonal, for a partition."""
+    blk = np.empty(n, np.int64)
+    for b in range(len(bptr) - 1):
+        blk[perm[bptr[b]:bptr[b + 1]]] = b
+    sizes = np.diff(bptr)
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    pairs = set(zip(blk[rows].tolist(), blk[np.asarray(col)].tolist())) | {(b, b) for b in range(len(sizes))}
+    return len(col) / float(sum(int(sizes[a]) * int(sizes[b]) for a, b in pairs))

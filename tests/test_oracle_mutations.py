@@ -42,6 +42,10 @@ MUTATIONS = {
     "weighted_order_ascending": ("if (a->w > b->w) return -1;\n    if (a->w < b->w) return 1;",
                                  "if (a->w > b->w) return 1;\n    if (a->w < b->w) return -1;"),
     "weighted_order_no_diag_norm_root": ("double f = sqrt(ss);", "double f = ss;"),
+    "graph_strict_threshold": ("if ((double)nnz >= mu * (double)el) {", "if ((double)nnz > mu * (double)el) {"),
+    "graph_row_adjacency_only": ("{ adj[af[i]++] = col[k]; adj[af[col[k]]++] = i; }", "{ adj[af[i]++] = col[k]; }"),
+    "graph_candidates_descending": ("while (b >= 0 && first[cand[b]] > first[v])", "while (b >= 0 && first[cand[b]] < first[v])"),
+    "graph_no_diagonal_blocks": ("        stamp[I] = I;\n        elems += (int64_t)sz[I] * sz[I];\n", ""),
     "apply_wrong_output_scale": ("x[A->rb[J] + r] = L->s2[A->rb[J] + r] * z[L->rest_rb[j] + r];",
                                  "x[A->rb[J] + r] = L->s1[A->rb[J] + r] * z[L->rest_rb[j] + r];"),
     "apply_skips_g_correction": ("yi[r] = yi[r] - gb[r * nK + q] * z[L->rest_rb[K] + q];", "yi[r] = yi[r];"),

@@ -462,6 +462,65 @@ def test_last_level_ilut_dropping_matches_dense_bruteforce(orc, case):
 
 
 # --------------------------------------------------------------------------------------
+# Graph-based compression (Sec. 2.2, Alg. 1)
+# --------------------------------------------------------------------------------------
+def _no_diagonal_matrix(seed, n=40):
+    """A random sparse pattern with no stored diagonal entry (rows couple only to others)."""
+    rng = np.random.default_rng(650 + seed)
+    pat = rng.random((n, n)) < 0.08
+    np.fill_diagonal(pat, False)
+    pat[np.arange(n), (np.arange(n) + 1) % n] = True
+    rows, cols = np.nonzero(pat)
+    rowptr = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=n))]).astype(np.int64)
+    return synth.System(n, rowptr, cols.astype(np.int32), rng.standard_normal(rows.size), np.zeros(n),
+                        np.ones(n, np.int32), name=f"nodiag-{seed}")
+
+
+_GRAPH_INPUTS = {
+    "no_diagonal": _no_diagonal_matrix,
+    "grid14": lambda seed: synth.grid_system(3, 3, 2, ell=3, stencil="14rand", perturb=0.15, seed=600 + seed),
+    "random": lambda seed: synth.random_pattern_matrix(60, 0.05, twins=15, seed=610 + seed),
+    "upwind": lambda seed: synth.upwind_system(3, 3, 2, perturb=0.1, seed=620 + seed),
+}
+
+
+@pytest.mark.parametrize("mu", [0.9, 0.7, 0.5])
+@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("kind", sorted(_GRAPH_INPUTS))
+def test_graph_compression_matches_bruteforce(orc, kind, seed, mu):
+    """Same partition as a set-based restatement of the greedy merging; every decision away
+    from the threshold except exact ties, which both sides accept (nnz >= mu * elements)."""
+    s = _GRAPH_INPUTS[kind](seed)
+    perm, bptr = orc.graph_compress(s.n, s.rowptr, s.col, mu)
+    p2, b2, margin = H.graph_compress_bruteforce(s.n, s.rowptr, s.col, mu)
+    assert margin == 0.0 or margin > 1e-9
+    np.testing.assert_array_equal(perm, p2)
+    np.testing.assert_array_equal(bptr, b2)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_graph_compression_mu_one_keeps_identical_pattern_classes(orc, seed):
+    s = synth.random_pattern_matrix(120, 0.04, twins=40, seed=630 + seed)
+    perm, bptr = orc.graph_compress(s.n, s.rowptr, s.col, 1.0)
+    p2, b2 = H.identical_pattern_partition(s.n, s.rowptr, s.col)
+    np.testing.assert_array_equal(perm, p2)
+    np.testing.assert_array_equal(bptr, b2)
+
+
+@pytest.mark.parametrize("mu", [0.9, 0.7, 0.6])
+def test_graph_compression_keeps_the_density_and_merges(orc, mu):
+    """The average block density of the result is at least mu (the method's guarantee),
+    blocks stay within 32 rows, and merging happened beyond the identical-pattern classes."""
+    s = synth.grid_system(6, 5, 4, ell=4, stencil="14rand", perturb=0.15, seed=640)
+    perm, bptr = orc.graph_compress(s.n, s.rowptr, s.col, mu)
+    assert sorted(perm.tolist()) == list(range(s.n))
+    assert H.average_block_density(s.n, s.rowptr, s.col, perm, bptr) >= mu
+    assert np.diff(bptr).max() <= 32
+    p1, b1 = H.identical_pattern_partition(s.n, s.rowptr, s.col)
+    assert len(bptr) < len(b1)
+
+
+# --------------------------------------------------------------------------------------
 # Preconditioner application (Alg. 2)
 # --------------------------------------------------------------------------------------
 @pytest.mark.parametrize("levels", [0, 1, 2, 3])

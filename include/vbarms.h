@@ -150,6 +150,18 @@ const char *vbarms_last_error(vbarms_t h);
 int vbarms_compress(vbarms_t h, const vbarms_csr *A, double tau,
                     int32_t *perm, int32_t *bptr, vbarms_cstats *st);
 
+/* Graph-based compression (Sec. 2.2, Alg. 1): rows with identical patterns form the first
+ * supernodes; then every supernode, in ascending order of its smallest row, tries the
+ * supernodes adjacent to it in the quotient graph of A + A^T (ascending smallest row) and
+ * merges with each one while the average block density of the whole ordering -- nnz(A)
+ * over the elements of the blocks holding an entry or lying on the diagonal -- stays at
+ * least mu; merges beyond VBARMS_MAX_BLOCK rows are skipped.  Blocks follow their smallest
+ * row.  mu in (0, 1]; mu = 1 keeps the identical-pattern classes.  The merge loop is
+ * sequential by definition and runs on the host over a copy of the pattern.  Outputs and
+ * errors as vbarms_compress. */
+int vbarms_compress_graph(vbarms_t h, const vbarms_csr *A, double mu,
+                          int32_t *perm, int32_t *bptr, vbarms_cstats *st);
+
 /* Uses a given block partition instead of computing one: perm[n], bptr[p+1] are DEVICE
  * arrays with the same meaning as the outputs of vbarms_compress. */
 int vbarms_set_partition(vbarms_t h, const vbarms_csr *A, const int32_t *perm,

@@ -440,6 +440,35 @@ int vbarms_compress(vbarms_t h, const vbarms_csr *A, double tau, int32_t *perm, 
     });
 }
 
+int vbarms_compress_graph(vbarms_t h, const vbarms_csr *A, double mu, int32_t *perm, int32_t *bptr,
+                          vbarms_cstats *st) {
+    return guarded(h, [&] {
+        validate_csr(A);
+        if (!(mu > 0.0 && mu <= 1.0)) fail(VBARMS_ERR_ARG, "mu must lie in (0, 1]");
+        hipStream_t s = h->stream;
+        Timer tm(s);
+        h->n = A->n;
+        h->nnz = A->nnz;
+        std::vector<int64_t> rp;
+        std::vector<int> ci;
+        to_host(rp, A->rowptr, (size_t)A->n + 1, s);
+        to_host(ci, A->col, (size_t)A->nnz, s);
+        for (int64_t k = 0; k < A->nnz; ++k)
+            if (ci[k] < 0 || ci[k] >= A->n) fail(VBARMS_ERR_ARG, "column index out of range");
+        std::vector<int> hperm;
+        h->bptr = graph_compress_host(A->n, rp, ci, mu, hperm);
+        h->perm.alloc(std::max(A->n, 1));
+        to_device(h->perm.p, hperm.data(), hperm.size(), s);
+        finish_partition(h, A, st);
+        if (perm && A->n) VB_HIP(hipMemcpyAsync(perm, h->perm.p, sizeof(int) * A->n, hipMemcpyDeviceToDevice, s));
+        if (bptr) to_device(bptr, h->bptr.data(), h->bptr.size(), s);
+        VB_HIP(hipStreamSynchronize(s));  // host vectors are copy sources
+        h->stats.compress_ms = tm.stop();
+        h->stats.nnz = A->nnz;
+        return VBARMS_OK;
+    });
+}
+
 int vbarms_set_partition(vbarms_t h, const vbarms_csr *A, const int32_t *perm, const int32_t *bptr, int32_t p,
                          vbarms_cstats *st) {
     return guarded(h, [&] {

@@ -91,6 +91,10 @@ struct DevErr {
 void lfmis(int nv, const int64_t *eptr, const int *elist, const int64_t *eptr2, const int *elist2, const double *prio,
            int *state, hipStream_t s);
 std::vector<int> compress_gpu(int n, const int64_t *rowptr, const int *col, double tau, int *perm, hipStream_t s);
+// Graph-based compression with target average block density mu on a host copy of the
+// pattern; returns the block offsets and fills perm (new position -> original row).
+std::vector<int> graph_compress_host(int n, const std::vector<int64_t> &rp, const std::vector<int> &ci, double mu,
+                                     std::vector<int> &perm);
 void panel_from_csr(int n, const int64_t *rowptr, const int *col, const double *val, const int *perm,
                     const std::vector<int> &bptr, Panel<double> &out, int *err, hipStream_t s);
 template <class T>

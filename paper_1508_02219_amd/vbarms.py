@@ -80,6 +80,7 @@ SIGNATURES = {
     "vbarms_last_error": (C.c_char_p, [_P]),
     "vbarms_compress": (C.c_int, [_P, C.POINTER(_Csr), C.c_double, _P, _P, C.POINTER(CStats)]),
     "vbarms_set_partition": (C.c_int, [_P, C.POINTER(_Csr), _P, _P, C.c_int32, C.POINTER(CStats)]),
+    "vbarms_compress_graph": (C.c_int, [_P, C.POINTER(_Csr), C.c_double, _P, _P, C.POINTER(CStats)]),
     "vbarms_factor": (C.c_int, [_P, C.POINTER(_FParams)]),
     "vbarms_error_location": (C.c_int, [_P, _P, _P]),
     "vbarms_apply": (C.c_int, [_P, _P, _P]),
@@ -227,6 +228,19 @@ class Solver:
         st = CStats()
         self._check(lib().vbarms_compress(self.h, C.byref(A), float(tau), _dev_ptr(perm, torch.int32),
                                           _dev_ptr(bptr, torch.int32), C.byref(st)))
+        self.n = n
+        return perm[:n], bptr[: st.nblocks + 1], st
+
+    def compress_graph(self, rowptr, col, val, mu):
+        """Graph-based compression with target block density mu (Sec. 2.2, Alg. 1)."""
+        torch = self._torch
+        A = self._csr(rowptr, col, val)
+        n = A.n
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=rowptr.device)
+        bptr = torch.empty(n + 1, dtype=torch.int32, device=rowptr.device)
+        st = CStats()
+        self._check(lib().vbarms_compress_graph(self.h, C.byref(A), float(mu), _dev_ptr(perm, torch.int32),
+                                                _dev_ptr(bptr, torch.int32), C.byref(st)))
         self.n = n
         return perm[:n], bptr[: st.nblocks + 1], st
 

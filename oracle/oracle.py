@@ -45,7 +45,7 @@ def lib():
         l.orc_compress.restype = C.c_int
         l.orc_graph_compress.argtypes = [C.c_int, P, P, dbl, P, P, P]
         l.orc_graph_compress.restype = C.c_int
-        l.orc_build.argtypes = [C.c_int, P, P, P, P, P, C.c_int, C.c_int, P, C.c_int, C.c_int]
+        l.orc_build.argtypes = [C.c_int, P, P, P, P, P, C.c_int, C.c_int, P, C.c_int, C.c_int, C.c_int]
         l.orc_build.restype = P
         l.orc_free.argtypes = [P]
         l.orc_status.argtypes = [P, P, P]
@@ -58,6 +58,7 @@ def lib():
         l.orc_nlevels.restype = C.c_int
         l.orc_level_info.argtypes = [P, C.c_int, P]
         l.orc_level_is.argtypes = [P, C.c_int, P]
+        l.orc_level_groups.argtypes = [P, C.c_int, P]
         l.orc_level_scaling.argtypes = [P, C.c_int, P, P]
         l.orc_matrix_dims.argtypes = [P, C.c_int, C.c_int, P]
         l.orc_matrix_dims.restype = C.c_int
@@ -139,7 +140,7 @@ class BlockMatrix:
 class Oracle:
     """Sequential FP64 VBARMS: compression result in, factors and solves out."""
 
-    def __init__(self, n, rowptr, col, val, perm, bptr, levels, droptol, drop_schur=1, is_order=0):
+    def __init__(self, n, rowptr, col, val, perm, bptr, levels, droptol, drop_schur=1, is_order=0, group_rows=0):
         rp, ci, v = _csr(rowptr, col, val)
         perm = np.ascontiguousarray(perm, dtype=np.int32)
         bptr = np.ascontiguousarray(bptr, dtype=np.int32)
@@ -151,7 +152,7 @@ class Oracle:
         self.n = n
         self._keep = (rp, ci, v, perm, bptr, dt)
         self.h = lib().orc_build(n, _p(rp), _p(ci), _p(v), _p(perm), _p(bptr), len(bptr) - 1,
-                                 levels, _p(dt), drop_schur, is_order)
+                                 levels, _p(dt), drop_schur, is_order, group_rows)
         el = np.zeros(1, np.int32)
         eb = np.zeros(1, np.int32)
         self.status = lib().orc_status(self.h, _p(el), _p(eb))
@@ -167,15 +168,24 @@ class Oracle:
         return lib().orc_nlevels(self.h)
 
     def level_info(self, l):
-        info = np.zeros(4, np.int32)
+        """p, n, nis (groups = pivot blocks of D), n_is, nis_sn (supernodes in the groups)."""
+        info = np.zeros(5, np.int32)
         lib().orc_level_info(self.h, l, _p(info))
-        return dict(p=int(info[0]), n=int(info[1]), nis=int(info[2]), n_is=int(info[3]))
+        return dict(p=int(info[0]), n=int(info[1]), nis=int(info[2]), n_is=int(info[3]), nis_sn=int(info[4]))
 
     def level_is(self, l):
-        k = self.level_info(l)["nis"]
+        """The supernodes of the independent set, group after group."""
+        k = self.level_info(l)["nis_sn"]
         out = np.zeros(max(k, 1), np.int32)
         lib().orc_level_is(self.h, l, _p(out))
         return out[:k]
+
+    def level_groups(self, l):
+        """Group pointers into level_is(l): group g is level_is(l)[gptr[g]:gptr[g+1]]."""
+        k = self.level_info(l)["nis"]
+        out = np.zeros(k + 1, np.int32)
+        lib().orc_level_groups(self.h, l, _p(out))
+        return out
 
     def level_scaling(self, l):
         n = self.level_info(l)["n"]

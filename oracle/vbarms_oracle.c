@@ -34,6 +34,15 @@
  *     descending w_I = ||A_II||_F / sum_J ||A_IJ||_F of the scaled matrix, so rows whose
  *     diagonal block dominates enter the independent set first; ties in ascending I.
  *     The set is still listed in ascending supernode order in P_I.
+ *  R8 (Sec. 2 and Sec. 3, Step 3, groups of nodes) with a group limit gmax > 0 an
+ *     unmarked supernode v opens a group and its unmarked quotient-graph neighbours join
+ *     it in ascending order, each one that keeps the group within gmax rows (larger ones
+ *     are skipped, later ones may still join); then the members and all their neighbours
+ *     are marked.  gmax = 0 is R3 (v alone).  Groups are listed by their smallest
+ *     supernode, members ascending; the group is one dense pivot block D_i (zero padded
+ *     where no block is stored), factored exactly by GEPP, and the blocks of L^{-1}F and
+ *     E U^{-1} are the group's rows (columns) against one remaining supernode, so R4
+ *     tests them at that size.
  */
 #include <math.h>
 #include <stdint.h>
@@ -498,17 +507,21 @@ static void build_vbcsr(int n, const int64_t *rowptr, const int32_t *col, const 
 /* ------------------------------------------------------------------------- */
 typedef struct {
     int p, n;            /* supernodes / scalar size of A_l */
-    int nis, n_is;       /* IS supernodes / IS scalar size */
+    int nis, n_is;       /* groups (pivot blocks of D) / IS scalar size */
+    int nis_sn;          /* supernodes in the groups */
     bmat A;              /* A_l as received (unscaled) */
     bmat As;             /* S1 A_l S2 */
     double *s1, *s2;     /* scaling */
-    int *is_list;        /* IS supernodes ascending (level numbering) */
+    int *is_list;        /* IS supernodes: the members of group 0, group 1, ... (R8) */
+    int *gptr;           /* [nis+1] group g holds is_list[gptr[g] .. gptr[g+1]) */
     int *rest_list;      /* remaining supernodes ascending */
     double *dlu;         /* LU of the IS diagonal blocks, concatenated in IS order */
     int64_t *dlu_off;    /* [nis+1] */
     int *dpiv;           /* pivots, concatenated (offsets = scalar offsets of IS blocks) */
-    int *is_rb;          /* scalar offsets of IS blocks [nis+1] */
-    int *rest_rb;        /* scalar offsets of remaining blocks [p-nis+1] */
+    int *is_rb;          /* scalar offsets of the groups [nis+1] */
+    int *rest_rb;        /* scalar offsets of remaining blocks [nrest+1] */
+    int *is_rows;        /* [n_is] level row of every row of D, group by group */
+    int *rest_rows;      /* [n - n_is] level row of every row of C */
     bmat G;              /* L^{-1} P F  (IS rows, remaining columns) */
     bmat W;              /* E U^{-1}    (remaining rows, IS columns) */
 } olevel;
@@ -614,10 +627,11 @@ static void weighted_order(const bmat *A, int *order) {
     free(nodes);
 }
 
-/* Step 3 (R3): greedy independent set on the quotient graph of A + A^T, visiting the
- * supernodes in natural order (is_order 0) or by the weights above (is_order 1) */
-static void level_indset(olevel *L, int *is_flag, int is_order) {
-    const bmat *A = &L->As;
+/* Step 3 (R3, R8): greedy block independent set on the quotient graph of A + A^T,
+ * visiting the supernodes in natural order (is_order 0) or by the weights above
+ * (is_order 1).  gid[I] receives the group of I in opening order, or -1 for the
+ * remaining supernodes; returns the number of groups. */
+static int level_groups(const bmat *A, int gmax, int is_order, int *gid) {
     int p = A->p;
     /* transpose pattern so that both (I,J) and (J,I) mark neighbours */
     int64_t *tp = xcalloc((size_t)p + 1, sizeof(int64_t));
@@ -631,105 +645,202 @@ static void level_indset(olevel *L, int *is_flag, int is_order) {
     free(f);
     char *marked = xcalloc((size_t)p + 1, 1);
     int *order = xmalloc(sizeof(int) * (size_t)(p ? p : 1));
+    int *nbr = xmalloc(sizeof(int) * (2 * (size_t)A->nb + 1));
+    int *mem = xmalloc(sizeof(int) * (size_t)(p ? p : 1));
     if (is_order == 1) weighted_order(A, order);
     else for (int I = 0; I < p; ++I) order[I] = I;
-    for (int I = 0; I < p; ++I) is_flag[I] = 0;
+    for (int I = 0; I < p; ++I) gid[I] = -1;
+    int ng = 0;
     for (int q = 0; q < p; ++q) {
-        int I = order[q];
-        if (marked[I]) continue;
-        is_flag[I] = 1;
-        marked[I] = 1;
-        for (int64_t k = A->rp[I]; k < A->rp[I + 1]; ++k) marked[A->ci[k]] = 1;
-        for (int64_t k = tp[I]; k < tp[I + 1]; ++k) marked[tr[k]] = 1;
+        int v = order[q];
+        if (marked[v]) continue;
+        int g = ng++, nm = 0, rows = bm_rs(A, v);
+        gid[v] = g;
+        marked[v] = 1;
+        mem[nm++] = v;
+        if (gmax > 0) {
+            /* neighbours of v, ascending: its row pattern and its column pattern */
+            int nn = 0;
+            for (int64_t k = A->rp[v]; k < A->rp[v + 1]; ++k) nbr[nn++] = A->ci[k];
+            for (int64_t k = tp[v]; k < tp[v + 1]; ++k) nbr[nn++] = tr[k];
+            qsort(nbr, (size_t)nn, sizeof(int), cmp_int);
+            for (int a = 0; a < nn; ++a) {
+                int u = nbr[a];
+                if (marked[u]) continue;
+                if (rows + bm_rs(A, u) > gmax) continue;
+                gid[u] = g;
+                marked[u] = 1;
+                mem[nm++] = u;
+                rows += bm_rs(A, u);
+            }
+        }
+        for (int a = 0; a < nm; ++a) {
+            int I = mem[a];
+            for (int64_t k = A->rp[I]; k < A->rp[I + 1]; ++k) marked[A->ci[k]] = 1;
+            for (int64_t k = tp[I]; k < tp[I + 1]; ++k) marked[tr[k]] = 1;
+        }
     }
-    free(tp); free(tr); free(marked); free(order);
+    free(tp); free(tr); free(marked); free(order); free(nbr); free(mem);
+    return ng;
 }
 
 /* Steps 3-4 on one level; produces A_{l+1} in *next */
-static int level_factor(olevel *L, double t, int drop_schur, int is_order, bmat *next, int *err_block) {
+static int level_factor(olevel *L, double t, int drop_schur, int is_order, int gmax, bmat *next, int *err_block) {
     const bmat *A = &L->As;
     int p = A->p;
-    int *is_flag = xmalloc(sizeof(int) * (size_t)(p ? p : 1));
-    level_indset(L, is_flag, is_order);
-    /* P_I: independent set ascending, then the rest ascending */
+    int *gid = xmalloc(sizeof(int) * (size_t)(p ? p : 1));
+    int ng = level_groups(A, gmax, is_order, gid);
+    /* P_I: the groups by their smallest supernode, members ascending, then the rest
+     * ascending.  num[I] = group of I or position among the rest; goff[I] = scalar offset
+     * of an IS supernode inside its group. */
+    int *gnew = xmalloc(sizeof(int) * (size_t)(ng ? ng : 1));
+    for (int g = 0; g < ng; ++g) gnew[g] = -1;
+    int seen = 0;
+    for (int I = 0; I < p; ++I)
+        if (gid[I] >= 0 && gnew[gid[I]] < 0) gnew[gid[I]] = seen++;
+    for (int I = 0; I < p; ++I)
+        if (gid[I] >= 0) gid[I] = gnew[gid[I]];
+    free(gnew);
     int *num = xmalloc(sizeof(int) * (size_t)(p ? p : 1));
-    L->nis = 0;
-    for (int I = 0; I < p; ++I) if (is_flag[I]) L->nis++;
-    int nrest = p - L->nis;
-    L->is_list = xmalloc(sizeof(int) * (size_t)(L->nis ? L->nis : 1));
+    int *goff = xmalloc(sizeof(int) * (size_t)(p ? p : 1));
+    L->nis = ng;
+    L->gptr = xcalloc((size_t)ng + 1, sizeof(int));
+    L->nis_sn = 0;
+    for (int I = 0; I < p; ++I)
+        if (gid[I] >= 0) { L->gptr[gid[I] + 1]++; L->nis_sn++; }
+    for (int g = 0; g < ng; ++g) L->gptr[g + 1] += L->gptr[g];
+    int nrest = p - L->nis_sn;
+    L->is_list = xmalloc(sizeof(int) * (size_t)(L->nis_sn ? L->nis_sn : 1));
     L->rest_list = xmalloc(sizeof(int) * (size_t)(nrest ? nrest : 1));
-    L->is_rb = xmalloc(sizeof(int) * ((size_t)L->nis + 1));
+    L->is_rb = xcalloc((size_t)ng + 1, sizeof(int));
     L->rest_rb = xmalloc(sizeof(int) * ((size_t)nrest + 1));
-    int a = 0, b = 0;
-    L->is_rb[0] = 0; L->rest_rb[0] = 0;
+    int *fill = xmalloc(sizeof(int) * (size_t)(ng ? ng : 1));
+    for (int g = 0; g < ng; ++g) fill[g] = L->gptr[g];
+    int b = 0;
+    L->rest_rb[0] = 0;
     for (int I = 0; I < p; ++I) {
         int m = bm_rs(A, I);
-        if (is_flag[I]) { L->is_list[a] = I; num[I] = a; L->is_rb[a + 1] = L->is_rb[a] + m; a++; }
-        else { L->rest_list[b] = I; num[I] = b; L->rest_rb[b + 1] = L->rest_rb[b] + m; b++; }
+        if (gid[I] >= 0) {
+            int g = gid[I];
+            L->is_list[fill[g]++] = I;
+            num[I] = g;
+            goff[I] = L->is_rb[g + 1];
+            L->is_rb[g + 1] += m;
+        } else { L->rest_list[b] = I; num[I] = b; L->rest_rb[b + 1] = L->rest_rb[b] + m; b++; }
     }
-    L->n_is = L->is_rb[L->nis];
+    free(fill);
+    for (int g = 0; g < ng; ++g) L->is_rb[g + 1] += L->is_rb[g];
+    L->n_is = L->is_rb[ng];
+    L->is_rows = xmalloc(sizeof(int) * ((size_t)L->n_is + 1));
+    L->rest_rows = xmalloc(sizeof(int) * ((size_t)(L->n - L->n_is) + 1));
+    for (int g = 0; g < ng; ++g)
+        for (int a = L->gptr[g]; a < L->gptr[g + 1]; ++a) {
+            int I = L->is_list[a];
+            for (int r = 0; r < bm_rs(A, I); ++r) L->is_rows[L->is_rb[g] + goff[I] + r] = A->rb[I] + r;
+        }
+    for (int j = 0; j < nrest; ++j) {
+        int J = L->rest_list[j];
+        for (int r = 0; r < bm_rs(A, J); ++r) L->rest_rows[L->rest_rb[j] + r] = A->rb[J] + r;
+    }
 
-    /* pivot blocks: GEPP of every D_i */
-    L->dlu_off = xmalloc(sizeof(int64_t) * ((size_t)L->nis + 1));
+    /* pivot blocks: every D_i assembled dense from the blocks among its members, then GEPP */
+    L->dlu_off = xmalloc(sizeof(int64_t) * ((size_t)ng + 1));
     L->dlu_off[0] = 0;
-    for (int i = 0; i < L->nis; ++i) {
-        int m = L->is_rb[i + 1] - L->is_rb[i];
-        L->dlu_off[i + 1] = L->dlu_off[i] + (int64_t)m * m;
+    for (int g = 0; g < ng; ++g) {
+        int m = L->is_rb[g + 1] - L->is_rb[g];
+        L->dlu_off[g + 1] = L->dlu_off[g] + (int64_t)m * m;
     }
-    L->dlu = xcalloc((size_t)L->dlu_off[L->nis] + 1, sizeof(double));
+    L->dlu = xcalloc((size_t)L->dlu_off[ng] + 1, sizeof(double));
     L->dpiv = xcalloc((size_t)L->n_is + 1, sizeof(int));
-    for (int i = 0; i < L->nis; ++i) {
-        int I = L->is_list[i], m = bm_rs(A, I);
-        int64_t k = bm_find(A, I, I);
-        double *d = L->dlu + L->dlu_off[i];
-        if (k >= 0) memcpy(d, bm_blk(A, k), sizeof(double) * m * m);
-        if (gepp(m, d, L->dpiv + L->is_rb[i]) != ORC_OK) {
-            *err_block = I;
-            free(is_flag); free(num);
+    for (int g = 0; g < ng; ++g) {
+        int m = L->is_rb[g + 1] - L->is_rb[g];
+        double *d = L->dlu + L->dlu_off[g];
+        for (int a = L->gptr[g]; a < L->gptr[g + 1]; ++a) {
+            int I = L->is_list[a], mI = bm_rs(A, I);
+            for (int64_t k = A->rp[I]; k < A->rp[I + 1]; ++k) {
+                int J = A->ci[k], nJ = bm_cs(A, J);
+                if (gid[J] != g) continue;
+                const double *blk = bm_blk(A, k);
+                for (int r = 0; r < mI; ++r)
+                    for (int c = 0; c < nJ; ++c) d[(goff[I] + r) * m + goff[J] + c] = blk[r * nJ + c];
+            }
+        }
+        if (gepp(m, d, L->dpiv + L->is_rb[g]) != ORC_OK) {
+            *err_block = L->is_list[L->gptr[g]];
+            free(gid); free(num); free(goff);
             return ORC_ERR_SINGULAR;
         }
     }
 
-    /* G = L^{-1} P F, row by row of the independent set, block by block */
-    bm_init(&L->G, L->nis, L->is_rb, nrest, L->rest_rb);
+    /* G = L^{-1} P F, group by group; a block is the group's rows against one remaining
+     * supernode, stacked from the members' blocks */
+    bm_init(&L->G, ng, L->is_rb, nrest, L->rest_rb);
     double *tmp = NULL, *colv = NULL;
     int64_t tcap = 0;
-    for (int i = 0; i < L->nis; ++i) {
-        int I = L->is_list[i], m = bm_rs(A, I);
-        const double *d = L->dlu + L->dlu_off[i];
-        const int *pv = L->dpiv + L->is_rb[i];
+    int *cols = xmalloc(sizeof(int) * (size_t)(A->nb ? A->nb : 1));
+    for (int g = 0; g < ng; ++g) {
+        int m = L->is_rb[g + 1] - L->is_rb[g];
+        const double *d = L->dlu + L->dlu_off[g];
+        const int *pv = L->dpiv + L->is_rb[g];
         colv = xrealloc(colv, sizeof(double) * (size_t)m);
-        for (int64_t k = A->rp[I]; k < A->rp[I + 1]; ++k) {
-            int J = A->ci[k];
-            if (is_flag[J]) continue;
-            int nJ = bm_cs(A, J);
+        int nc = 0;
+        for (int a = L->gptr[g]; a < L->gptr[g + 1]; ++a) {
+            int I = L->is_list[a];
+            for (int64_t k = A->rp[I]; k < A->rp[I + 1]; ++k)
+                if (gid[A->ci[k]] < 0) cols[nc++] = num[A->ci[k]];
+        }
+        qsort(cols, (size_t)nc, sizeof(int), cmp_int);
+        for (int e = 0; e < nc; ++e) {
+            if (e > 0 && cols[e] == cols[e - 1]) continue;
+            int K = cols[e], J = L->rest_list[K], nJ = bm_cs(A, J);
             if ((int64_t)m * nJ > tcap) { tcap = (int64_t)m * nJ; tmp = xrealloc(tmp, sizeof(double) * tcap); }
-            const double *fb = bm_blk(A, k);
+            memset(tmp, 0, sizeof(double) * (size_t)m * nJ);
+            for (int a = L->gptr[g]; a < L->gptr[g + 1]; ++a) {
+                int I = L->is_list[a], mI = bm_rs(A, I);
+                int64_t k = bm_find(A, I, J);
+                if (k < 0) continue;
+                const double *fb = bm_blk(A, k);
+                for (int r = 0; r < mI; ++r)
+                    for (int c = 0; c < nJ; ++c) tmp[(goff[I] + r) * nJ + c] = fb[r * nJ + c];
+            }
             for (int c = 0; c < nJ; ++c) {
-                for (int r = 0; r < m; ++r) colv[r] = fb[r * nJ + c];
+                for (int r = 0; r < m; ++r) colv[r] = tmp[r * nJ + c];
                 lu_fwd(m, d, pv, colv);
                 for (int r = 0; r < m; ++r) tmp[r * nJ + c] = colv[r];
             }
-            if (!drop_block(m, nJ, tmp, t)) bm_push(&L->G, num[J], tmp);
+            if (!drop_block(m, nJ, tmp, t)) bm_push(&L->G, K, tmp);
         }
         bm_end_row(&L->G);
     }
-    /* W = E U^{-1}, row by row of the remaining supernodes */
-    bm_init(&L->W, nrest, L->rest_rb, L->nis, L->is_rb);
+    /* W = E U^{-1}, row by row of the remaining supernodes; a block is one remaining
+     * supernode's rows against a whole group, its members' blocks side by side */
+    bm_init(&L->W, nrest, L->rest_rb, ng, L->is_rb);
     for (int j = 0; j < nrest; ++j) {
         int J = L->rest_list[j], m = bm_rs(A, J);
-        for (int64_t k = A->rp[J]; k < A->rp[J + 1]; ++k) {
-            int I = A->ci[k];
-            if (!is_flag[I]) continue;
-            int nI = bm_cs(A, I);
-            if ((int64_t)m * nI > tcap) { tcap = (int64_t)m * nI; tmp = xrealloc(tmp, sizeof(double) * tcap); }
-            memcpy(tmp, bm_blk(A, k), sizeof(double) * m * nI);
-            const double *d = L->dlu + L->dlu_off[num[I]];
-            for (int r = 0; r < m; ++r) row_solve_u(nI, d, tmp + r * nI);
-            if (!drop_block(m, nI, tmp, t)) bm_push(&L->W, num[I], tmp);
+        int nc = 0;
+        for (int64_t k = A->rp[J]; k < A->rp[J + 1]; ++k)
+            if (gid[A->ci[k]] >= 0) cols[nc++] = gid[A->ci[k]];
+        qsort(cols, (size_t)nc, sizeof(int), cmp_int);
+        for (int e = 0; e < nc; ++e) {
+            if (e > 0 && cols[e] == cols[e - 1]) continue;
+            int g = cols[e], mg = L->is_rb[g + 1] - L->is_rb[g];
+            if ((int64_t)m * mg > tcap) { tcap = (int64_t)m * mg; tmp = xrealloc(tmp, sizeof(double) * tcap); }
+            memset(tmp, 0, sizeof(double) * (size_t)m * mg);
+            for (int64_t k = A->rp[J]; k < A->rp[J + 1]; ++k) {
+                int I = A->ci[k];
+                if (gid[I] != g) continue;
+                int nI = bm_cs(A, I);
+                const double *eb = bm_blk(A, k);
+                for (int r = 0; r < m; ++r)
+                    for (int c = 0; c < nI; ++c) tmp[r * mg + goff[I] + c] = eb[r * nI + c];
+            }
+            const double *d = L->dlu + L->dlu_off[g];
+            for (int r = 0; r < m; ++r) row_solve_u(mg, d, tmp + r * mg);
+            if (!drop_block(m, mg, tmp, t)) bm_push(&L->W, g, tmp);
         }
         bm_end_row(&L->W);
     }
+    free(cols);
     /* Schur complement A_{l+1} = C - W G (Eq. schurl), row by row */
     bm_init(next, nrest, L->rest_rb, nrest, L->rest_rb);
     int64_t *slot = xmalloc(sizeof(int64_t) * (size_t)(nrest ? nrest : 1));
@@ -744,7 +855,7 @@ static int level_factor(olevel *L, double t, int drop_schur, int is_order, bmat 
         /* C row */
         for (int64_t k = A->rp[J]; k < A->rp[J + 1]; ++k) {
             int K = A->ci[k];
-            if (is_flag[K]) continue;
+            if (gid[K] >= 0) continue;
             int nK = bm_cs(A, K);
             if (used + (int64_t)m * nK > acc_cap) { acc_cap = 2 * (used + (int64_t)m * nK); acc = xrealloc(acc, sizeof(double) * acc_cap); }
             slot[num[K]] = used;
@@ -786,7 +897,7 @@ static int level_factor(olevel *L, double t, int drop_schur, int is_order, bmat 
         bm_end_row(next);
     }
     free(acc); free(slot); free(keys); free(tmp); free(colv);
-    free(is_flag); free(num);
+    free(gid); free(num); free(goff);
     return ORC_OK;
 }
 
@@ -887,7 +998,7 @@ void orc_free(orc_t *h);
 
 orc_t *orc_build(int n, const int64_t *rowptr, const int32_t *col, const double *val,
                  const int32_t *perm, const int32_t *bptr, int p,
-                 int levels, const double *droptol, int drop_schur, int is_order) {
+                 int levels, const double *droptol, int drop_schur, int is_order, int group_rows) {
     orc_t *h = xcalloc(1, sizeof(orc_t));
     h->n = n; h->p = p;
     h->err_level = -1; h->err_block = -1;
@@ -895,7 +1006,7 @@ orc_t *orc_build(int n, const int64_t *rowptr, const int32_t *col, const double 
     h->bptr = xmalloc(sizeof(int32_t) * ((size_t)p + 1));
     memcpy(h->perm, perm, sizeof(int32_t) * (size_t)n);
     memcpy(h->bptr, bptr, sizeof(int32_t) * ((size_t)p + 1));
-    if (levels < 0 || levels > 16) { h->status = ORC_ERR_ARG; return h; }
+    if (levels < 0 || levels > 16 || group_rows < 0) { h->status = ORC_ERR_ARG; return h; }
     h->lev = xcalloc((size_t)levels + 1, sizeof(olevel));
     bmat cur;
     build_vbcsr(n, rowptr, col, val, perm, bptr, p, &cur);
@@ -908,7 +1019,7 @@ orc_t *orc_build(int n, const int64_t *rowptr, const int32_t *col, const double 
         level_scale(L);
         bmat next;
         int eb = -1;
-        int st = level_factor(L, droptol[l], drop_schur, is_order, &next, &eb);
+        int st = level_factor(L, droptol[l], drop_schur, is_order, group_rows, &next, &eb);
         h->nlev = l + 1;
         if (st != ORC_OK) { h->status = st; h->err_level = l; h->err_block = eb; memset(&h->last, 0, sizeof(bmat)); return h; }
         cur = next;
@@ -923,7 +1034,8 @@ orc_t *orc_build(int n, const int64_t *rowptr, const int32_t *col, const double 
 
 static void free_level(olevel *L) {
     bm_free(&L->A); bm_free(&L->As); bm_free(&L->G); bm_free(&L->W);
-    free(L->s1); free(L->s2); free(L->is_list); free(L->rest_list);
+    free(L->s1); free(L->s2); free(L->is_list); free(L->rest_list); free(L->gptr);
+    free(L->is_rows); free(L->rest_rows);
     free(L->dlu); free(L->dlu_off); free(L->dpiv); free(L->is_rb); free(L->rest_rb);
 }
 
@@ -988,24 +1100,25 @@ static void level_solve(const orc_t *h, int l, const double *b, double *x) {
         return;
     }
     const olevel *L = &h->lev[l];
-    const bmat *A = &L->As;
-    int nrest = L->p - L->nis;
+    int nrest = L->p - L->nis_sn;
     int nr = L->rest_rb[nrest];
     double *y = xmalloc(sizeof(double) * ((size_t)L->n_is + 1));
     double *g = xmalloc(sizeof(double) * ((size_t)nr + 1));
     double *z = xmalloc(sizeof(double) * ((size_t)nr + 1));
-    /* f = (S1 b) restricted to the independent set; y = L^{-1} P f per block */
+    /* f = (S1 b) restricted to the independent set; y = L^{-1} P f per group */
     for (int i = 0; i < L->nis; ++i) {
-        int I = L->is_list[i], m = bm_rs(A, I);
+        int m = L->is_rb[i + 1] - L->is_rb[i];
+        const int *rows = L->is_rows + L->is_rb[i];
         double *yi = y + L->is_rb[i];
-        for (int r = 0; r < m; ++r) yi[r] = L->s1[A->rb[I] + r] * b[A->rb[I] + r];
+        for (int r = 0; r < m; ++r) yi[r] = L->s1[rows[r]] * b[rows[r]];
         lu_fwd(m, L->dlu + L->dlu_off[i], L->dpiv + L->is_rb[i], yi);
     }
     /* g' = S1 g - W y */
     for (int j = 0; j < nrest; ++j) {
-        int J = L->rest_list[j], m = bm_rs(A, J);
+        int m = L->rest_rb[j + 1] - L->rest_rb[j];
+        const int *rows = L->rest_rows + L->rest_rb[j];
         double *gj = g + L->rest_rb[j];
-        for (int r = 0; r < m; ++r) gj[r] = L->s1[A->rb[J] + r] * b[A->rb[J] + r];
+        for (int r = 0; r < m; ++r) gj[r] = L->s1[rows[r]] * b[rows[r]];
         for (int64_t k = L->W.rp[j]; k < L->W.rp[j + 1]; ++k) {
             int i = L->W.ci[k];
             int mi = L->is_rb[i + 1] - L->is_rb[i];
@@ -1015,9 +1128,10 @@ static void level_solve(const orc_t *h, int l, const double *b, double *x) {
         }
     }
     level_solve(h, l + 1, g, z);
-    /* u = U^{-1} (y - G z) per block; x = S2 P_I^T (u, z) */
+    /* u = U^{-1} (y - G z) per group; x = S2 P_I^T (u, z) */
     for (int i = 0; i < L->nis; ++i) {
-        int I = L->is_list[i], m = bm_rs(A, I);
+        int m = L->is_rb[i + 1] - L->is_rb[i];
+        const int *rows = L->is_rows + L->is_rb[i];
         double *yi = y + L->is_rb[i];
         for (int64_t k = L->G.rp[i]; k < L->G.rp[i + 1]; ++k) {
             int K = L->G.ci[k];
@@ -1027,11 +1141,12 @@ static void level_solve(const orc_t *h, int l, const double *b, double *x) {
                 for (int q = 0; q < nK; ++q) yi[r] = yi[r] - gb[r * nK + q] * z[L->rest_rb[K] + q];
         }
         lu_bwd(m, L->dlu + L->dlu_off[i], yi);
-        for (int r = 0; r < m; ++r) x[A->rb[I] + r] = L->s2[A->rb[I] + r] * yi[r];
+        for (int r = 0; r < m; ++r) x[rows[r]] = L->s2[rows[r]] * yi[r];
     }
     for (int j = 0; j < nrest; ++j) {
-        int J = L->rest_list[j], m = bm_rs(A, J);
-        for (int r = 0; r < m; ++r) x[A->rb[J] + r] = L->s2[A->rb[J] + r] * z[L->rest_rb[j] + r];
+        int m = L->rest_rb[j + 1] - L->rest_rb[j];
+        const int *rows = L->rest_rows + L->rest_rb[j];
+        for (int r = 0; r < m; ++r) x[rows[r]] = L->s2[rows[r]] * z[L->rest_rb[j] + r];
     }
     free(y); free(g); free(z);
 }
@@ -1148,16 +1263,23 @@ enum { W_A = 0, W_AS = 1, W_G = 2, W_W = 3, W_D = 4, W_LAST = 5, W_L = 6, W_U = 
 
 int orc_nlevels(const orc_t *h) { return h->nlev; }
 
-/* info: p, n, nis, n_is */
+/* info: p, n, groups, n_is, supernodes in the groups */
 int orc_level_info(const orc_t *h, int l, int32_t *info) {
     if (l < 0 || l >= h->nlev) return ORC_ERR_ARG;
     const olevel *L = &h->lev[l];
-    info[0] = L->p; info[1] = L->n; info[2] = L->nis; info[3] = L->n_is;
+    info[0] = L->p; info[1] = L->n; info[2] = L->nis; info[3] = L->n_is; info[4] = L->nis_sn;
     return ORC_OK;
 }
+/* the supernodes of the groups, group after group (info[4] entries) */
 int orc_level_is(const orc_t *h, int l, int32_t *is_list) {
     if (l < 0 || l >= h->nlev) return ORC_ERR_ARG;
-    memcpy(is_list, h->lev[l].is_list, sizeof(int) * (size_t)h->lev[l].nis);
+    memcpy(is_list, h->lev[l].is_list, sizeof(int) * (size_t)h->lev[l].nis_sn);
+    return ORC_OK;
+}
+/* group pointers into the list above (info[2] + 1 entries) */
+int orc_level_groups(const orc_t *h, int l, int32_t *gptr) {
+    if (l < 0 || l >= h->nlev) return ORC_ERR_ARG;
+    memcpy(gptr, h->lev[l].gptr, sizeof(int) * ((size_t)h->lev[l].nis + 1));
     return ORC_OK;
 }
 int orc_level_scaling(const orc_t *h, int l, double *s1, double *s2) {

@@ -221,3 +221,29 @@ def average_block_density(n, rowptr, col, perm, bptr):
     rows = np.repeat(np.arange(n), np.diff(rowptr))
     pairs = set(zip(blk[rows].tolist(), blk[np.asarray(col)].tolist())) | {(b, b) for b in range(len(sizes))}
     return len(col) / float(sum(int(sizes[a]) * int(sizes[b]) for a, b in pairs))
+
+
+def greedy_groups_bruteforce(adj_sets, sizes, gmax, order=None):
+    """Greedy block independent set with groups of nodes on an undirected graph: an
+    unmarked vertex v opens a group, its unmarked neighbours join in ascending order when
+    the group stays within gmax rows, then the group and its neighbourhood are marked.
+    Returns the groups (members ascending) ordered by their smallest member."""
+    p = len(adj_sets)
+    marked = [False] * p
+    groups = []
+    for v in (range(p) if order is None else order):
+        if marked[v]:
+            continue
+        mem = [v]
+        marked[v] = True
+        rows = int(sizes[v])
+        for u in sorted(adj_sets[v]):
+            if not marked[u] and rows + int(sizes[u]) <= gmax:
+                mem.append(u)
+                marked[u] = True
+                rows += int(sizes[u])
+        for w in mem:
+            for u in adj_sets[w]:
+                marked[u] = True
+        groups.append(sorted(mem))
+    return sorted(groups, key=lambda g: g[0])

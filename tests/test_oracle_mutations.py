@@ -46,8 +46,19 @@ MUTATIONS = {
     "graph_row_adjacency_only": ("{ adj[af[i]++] = col[k]; adj[af[col[k]]++] = i; }", "{ adj[af[i]++] = col[k]; }"),
     "graph_candidates_descending": ("while (b >= 0 && first[cand[b]] > first[v])", "while (b >= 0 && first[cand[b]] < first[v])"),
     "graph_no_diagonal_blocks": ("        stamp[I] = I;\n        elems += (int64_t)sz[I] * sz[I];\n", ""),
-    "apply_wrong_output_scale": ("x[A->rb[J] + r] = L->s2[A->rb[J] + r] * z[L->rest_rb[j] + r];",
-                                 "x[A->rb[J] + r] = L->s1[A->rb[J] + r] * z[L->rest_rb[j] + r];"),
+    "apply_wrong_output_scale": ("x[rows[r]] = L->s2[rows[r]] * z[L->rest_rb[j] + r];",
+                                 "x[rows[r]] = L->s1[rows[r]] * z[L->rest_rb[j] + r];"),
+    "group_seed_neighbours_only": ("        for (int a = 0; a < nm; ++a) {\n            int I = mem[a];",
+                                   "        for (int a = 0; a < 1; ++a) {\n            int I = mem[a];"),
+    "group_cap_strict": ("if (rows + bm_rs(A, u) > gmax) continue;", "if (rows + bm_rs(A, u) >= gmax) continue;"),
+    "group_stop_at_first_misfit": ("if (rows + bm_rs(A, u) > gmax) continue;", "if (rows + bm_rs(A, u) > gmax) break;"),
+    "group_w_member_offset": ("tmp[r * mg + goff[I] + c] = eb[r * nI + c];", "tmp[r * mg + c] = eb[r * nI + c];"),
+    "group_g_member_offset": ("tmp[(goff[I] + r) * nJ + c] = fb[r * nJ + c];", "tmp[r * nJ + c] = fb[r * nJ + c];"),
+    "group_d_offsets_swapped": ("d[(goff[I] + r) * m + goff[J] + c] = blk[r * nJ + c];",
+                                "d[(goff[J] + r) * m + goff[I] + c] = blk[r * nJ + c];"),
+    "group_opening_order": ("        if (gid[I] >= 0) gid[I] = gnew[gid[I]];", "        if (gid[I] >= 0) gid[I] = gid[I];"),
+    "group_apply_reads_packed_rows": ("for (int r = 0; r < m; ++r) yi[r] = L->s1[rows[r]] * b[rows[r]];",
+                                      "for (int r = 0; r < m; ++r) yi[r] = L->s1[rows[r]] * b[L->is_rb[i] + r];"),
     "apply_skips_g_correction": ("yi[r] = yi[r] - gb[r * nK + q] * z[L->rest_rb[K] + q];", "yi[r] = yi[r];"),
     "last_solve_skips_l": ("for (int q = 0; q < nK; ++q) xi[r] = xi[r] - b[r * nK + q] * xk[q];\n        }\n    }\n    for (int i = p - 1;",
                            "for (int q = 0; q < nK; ++q) xi[r] = xi[r];\n        }\n    }\n    for (int i = p - 1;"),

@@ -377,6 +377,182 @@ def test_weighted_independent_set_matches_bruteforce(orc, maker, levels):
 
 
 # --------------------------------------------------------------------------------------
+# Groups of nodes in the block independent set (Sec. 2; Sec. 3 Step 3, D_i block sparse)
+# --------------------------------------------------------------------------------------
+_GROUP_INPUTS = {
+    "grid": (lambda: synth.grid_system(5, 4, 4, ell=4, stencil="14rand", perturb=0.1, seed=93), 0.8),
+    "upwind": (lambda: synth.upwind_system(5, 5, 4, seed=94), 1.0),
+    "random": (lambda: synth.random_pattern_matrix(160, 0.03, twins=30, seed=95, diag=6.0), 0.6),
+}
+
+
+def _group_oracle(orc, maker, levels, t, gmax, is_order=0):
+    mk, tau = _GROUP_INPUTS[maker]
+    s = mk()
+    perm, bptr = orc.compress(s.n, s.rowptr, s.col, tau)
+    return s, orc.Oracle(s.n, s.rowptr, s.col, s.val, perm, bptr, levels, t, 1, is_order, gmax)
+
+
+def _groups_of(o, lvl):
+    is_list, gptr = o.level_is(lvl), o.level_groups(lvl)
+    return [is_list[gptr[g]:gptr[g + 1]].tolist() for g in range(len(gptr) - 1)]
+
+
+def _weights_order(bm):
+    w = np.zeros(bm.p)
+    for i in range(bm.p):
+        norms = {int(bm.colidx[k]): np.linalg.norm(bm.block(k)) for k in range(bm.rowptr[i], bm.rowptr[i + 1])}
+        tot = sum(norms.values())
+        w[i] = norms.get(i, 0.0) / tot if tot > 0 else 0.0
+    return sorted(range(bm.p), key=lambda i: (-w[i], i))
+
+
+@pytest.mark.parametrize("is_order", [0, 1])
+@pytest.mark.parametrize("gmax", [12, 20, 32])
+@pytest.mark.parametrize("maker", sorted(_GROUP_INPUTS))
+def test_group_independent_sets_match_bruteforce(orc, maker, gmax, is_order):
+    """Every level: the groups of a set-based restatement of the greedy; no coupling between
+    two groups; every remaining supernode next to a group; members next to the group's
+    opener; groups within gmax rows unless the opener alone is larger."""
+    s, o = _group_oracle(orc, maker, 3, 1e-3, gmax, is_order)
+    assert o.status == 0
+    merged = 0
+    for lvl in range(o.nlevels):
+        a = o.matrix(orc.AS, lvl)
+        adj = H.quotient_adjacency(a)
+        sizes = np.diff(a.rb)
+        order = _weights_order(a) if is_order else None
+        got = _groups_of(o, lvl)
+        assert got == H.greedy_groups_bruteforce(adj, sizes, gmax, order)
+        owner = {v: g for g, mem in enumerate(got) for v in mem}
+        for v, g in owner.items():
+            assert all(owner.get(u, g) == g for u in adj[v])
+        assert all(v in owner or any(u in owner for u in adj[v]) for v in range(a.p))
+        pos = {v: k for k, v in enumerate(order)} if order else {v: v for v in range(a.p)}
+        for mem in got:
+            opener = min(mem, key=lambda v: pos[v])
+            assert all(v == opener or v in adj[opener] for v in mem)
+            rows = int(sum(sizes[v] for v in mem))
+            assert rows <= gmax or len(mem) == 1
+            merged += len(mem) > 1
+        info = o.level_info(lvl)
+        assert info["nis"] == len(got) and info["n_is"] == sum(int(sizes[v]) for g in got for v in g)
+    assert merged > 0
+
+
+def test_group_zero_is_the_singleton_set(orc):
+    s, og = _group_oracle(orc, "grid", 2, 1e-3, 0)
+    s2, o1 = _group_oracle(orc, "grid", 2, 1e-3, 0)
+    for lvl in range(og.nlevels):
+        assert all(len(g) == 1 for g in _groups_of(og, lvl))
+    x = np.random.default_rng(0).standard_normal(s.n)
+    np.testing.assert_array_equal(og.apply(x), o1.apply(x))
+
+
+def _group_rows(As, groups):
+    ri = [np.arange(As.rb[v], As.rb[v + 1]) for g in groups for v in g]
+    return np.concatenate(ri).astype(int) if ri else np.zeros(0, int)
+
+
+@pytest.mark.parametrize("gmax", [8, 20])
+@pytest.mark.parametrize("maker", ["grid", "random"])
+def test_group_zero_drop_factorization_identity(orc, maker, gmax):
+    """Eq. vbarms with groups at t = 0: [D F; E C] = [P^T L 0; W I] [U G; 0 S] with D block
+    diagonal over the groups, and S the exact Schur complement."""
+    s, o = _group_oracle(orc, maker, 1, 0.0, gmax)
+    assert o.status == 0
+    As = o.matrix(orc.AS, 0)
+    a = As.dense()
+    groups = _groups_of(o, 0)
+    assert max(len(g) for g in groups) > 1
+    ri = _group_rows(As, groups)
+    inset = {v for g in groups for v in g}
+    rr = np.concatenate([np.arange(As.rb[v], As.rb[v + 1]) for v in range(As.p) if v not in inset]).astype(int)
+    D, F, E, Cm = a[np.ix_(ri, ri)], a[np.ix_(ri, rr)], a[np.ix_(rr, ri)], a[np.ix_(rr, rr)]
+    S_exact = Cm - E @ np.linalg.solve(D, F)
+    S = o.matrix(orc.LAST).dense()
+    assert np.abs(S - S_exact).max() <= 1e-12 * np.abs(S_exact).max()
+    dm = o.matrix(orc.D, 0)
+    assert list(np.diff(dm.rb)) == [int(sum(np.diff(As.rb)[v] for v in g)) for g in groups]
+    PtL, Uu = _block_lu_parts(dm)
+    G = o.matrix(orc.G, 0).dense()
+    Wm = o.matrix(orc.W, 0).dense()
+    ni, nr = len(ri), len(rr)
+    left = np.block([[PtL, np.zeros((ni, nr))], [Wm, np.eye(nr)]])
+    right = np.block([[Uu, G], [np.zeros((nr, ni)), S]])
+    full = np.block([[D, F], [E, Cm]])
+    assert np.abs(left @ right - full).max() <= 1e-12 * np.abs(full).max()
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+@pytest.mark.parametrize("gmax", [10, 32])
+def test_group_apply_is_exact_inverse_without_dropping(orc, levels, gmax):
+    s, o = _group_oracle(orc, "upwind", levels, 0.0, gmax)
+    assert o.status == 0
+    x = np.random.default_rng(levels).standard_normal(s.n)
+    ye = np.linalg.solve(s.dense(), x)
+    assert np.abs(o.apply(x) - ye).max() <= 1e-10 * np.abs(ye).max()
+
+
+def test_group_dropping_matches_dense_bruteforce(orc):
+    """At 0 < t: a block of L^{-1}F is a group's rows against one remaining supernode and a
+    block of E U^{-1} one remaining supernode against a whole group; each is kept iff its
+    ||B||_F / (m n) >= t."""
+    t = 0.01
+    s, o = _group_oracle(orc, "grid", 1, [t, 0.0], 12)
+    assert o.status == 0
+    As = o.matrix(orc.AS, 0)
+    a = As.dense()
+    groups = _groups_of(o, 0)
+    owner = {v: g for g, mem in enumerate(groups) for v in mem}
+    rest = [v for v in range(As.p) if v not in owner]
+    rnum = {v: k for k, v in enumerate(rest)}
+    stored = {(i, int(As.colidx[k])) for i in range(As.p) for k in range(As.rowptr[i], As.rowptr[i + 1])}
+    dm = o.matrix(orc.D, 0)
+    PtL, Uu = _block_lu_parts(dm)
+    rows = lambda v: np.arange(As.rb[v], As.rb[v + 1])
+    Gx, Wx, margins = {}, {}, []
+    for g, mem in enumerate(groups):
+        rg = _group_rows(As, [mem])
+        lo, hi = dm.rb[g], dm.rb[g + 1]
+        for K in rest:
+            if not any((v, K) in stored for v in mem):
+                continue
+            val = np.linalg.solve(PtL[lo:hi, lo:hi], a[np.ix_(rg, rows(K))])
+            r = H.block_sumsq_ratio(val, t)
+            margins.append(abs(r - 1))
+            if r >= 1:
+                Gx[(g, rnum[K])] = val
+        for J in rest:
+            if not any((J, v) in stored for v in mem):
+                continue
+            val = np.linalg.solve(Uu[lo:hi, lo:hi].T, a[np.ix_(rows(J), rg)].T).T
+            r = H.block_sumsq_ratio(val, t)
+            margins.append(abs(r - 1))
+            if r >= 1:
+                Wx[(rnum[J], g)] = val
+    assert min(margins) > 1e-9
+
+    def blocks(bm):
+        return {(i, int(bm.colidx[k])): bm.block(k) for i in range(bm.p)
+                for k in range(bm.rowptr[i], bm.rowptr[i + 1])}
+
+    gb, wb = blocks(o.matrix(orc.G, 0)), blocks(o.matrix(orc.W, 0))
+    assert set(gb) == set(Gx) and set(wb) == set(Wx)
+    assert 0 < len(gb) < len(margins) and 0 < len(wb)
+    for key in Gx:
+        np.testing.assert_allclose(gb[key], Gx[key], rtol=1e-12, atol=1e-14)
+    for key in Wx:
+        np.testing.assert_allclose(wb[key], Wx[key], rtol=1e-12, atol=1e-14)
+
+
+def test_groups_eliminate_more_rows_per_level(orc):
+    s, og = _group_oracle(orc, "upwind", 1, 1e-3, 24)
+    s, o1 = _group_oracle(orc, "upwind", 1, 1e-3, 0)
+    assert og.level_info(0)["n_is"] > 1.25 * o1.level_info(0)["n_is"]
+
+
+# --------------------------------------------------------------------------------------
 # Last level block ILUT (Sec. 3, Alg. 3)
 # --------------------------------------------------------------------------------------
 def test_last_level_ilut_exact_without_dropping(orc):

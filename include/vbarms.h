@@ -90,6 +90,17 @@ typedef struct {
  * of size m x n is dropped when ||B||_F / (m n) < t); droptol[levels] is used by the
  * last-level block ILUT.  drop_schur = 1 also drops small off-diagonal blocks of every
  * Schur complement; 0 keeps them all (the paper's wording for intermediate levels).
+ *
+ * group_rows selects the groups of the block independent set (Sec. 2 and Sec. 3, Step 3,
+ * where the diagonal blocks D_i of D are themselves block sparse): 0 puts one supernode in
+ * every group; k in [1, VBARMS_MAX_BLOCK] lets an unmarked supernode v open a group that
+ * its unmarked quotient-graph neighbours (A + A^T) join in ascending order whenever the
+ * group stays within k rows, after which the members and all their neighbours are marked.
+ * A group is one dense pivot block, zero padded where no block is stored, factored exactly
+ * by GEPP; a block of L^{-1}F (E U^{-1}) is the group's rows (columns) against one remaining
+ * supernode, and the drop rule applies at that size.  The greedy is sequential by
+ * definition and runs on the host over a copy of the level's block pattern.
+ *
  * Zero-initialize the struct: 0 selects the default of every field. */
 typedef struct {
     int32_t levels;                        /* number of Schur reductions (0 = block ILUT only) */
@@ -97,6 +108,7 @@ typedef struct {
     int32_t drop_schur;
     int32_t is_order;                      /* VBARMS_IS_NATURAL or VBARMS_IS_WEIGHTED */
     int32_t precision;                     /* VBARMS_F64 or VBARMS_F32 */
+    int32_t group_rows;                    /* 0: one supernode per group; else the row limit */
 } vbarms_fparams;
 
 typedef struct {
@@ -320,10 +332,14 @@ int vbarms_kernel_stats(vbarms_t h, vbarms_kstat *out);
 
 /* levels actually factored */
 int vbarms_num_levels(vbarms_t h, int32_t *levels);
-/* info[4] = {p, n, nis, n_is} of level l */
+/* info[5] = {p, n, nis, n_is, nis_sn} of level l: supernodes, rows, groups (pivot blocks
+ * of D), rows of D, supernodes in the groups */
 int vbarms_level_info(vbarms_t h, int32_t level, int32_t *info);
-/* independent-set supernodes of level l, ascending (length nis) */
+/* the independent-set supernodes of level l, group after group, members ascending, groups
+ * by their smallest supernode (length nis_sn) */
 int vbarms_level_is(vbarms_t h, int32_t level, int32_t *is_list);
+/* gptr[nis+1]: group g is is_list[gptr[g] .. gptr[g+1]) */
+int vbarms_level_groups(vbarms_t h, int32_t level, int32_t *gptr);
 /* scaling vectors S1, S2 of level l (length n of the level) */
 int vbarms_level_scaling(vbarms_t h, int32_t level, double *s1, double *s2);
 /* dims[4] = {block rows, block columns, blocks, values} */

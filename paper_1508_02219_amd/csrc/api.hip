@@ -190,8 +190,8 @@ int factor_impl(vbarms_t h, const vbarms_fparams *p, std::unique_ptr<Factors<T>>
         Timer tm(s);
         f.lev.emplace_back();
         Panel<T> next;
-        factor_level<T>(f.lev[l], std::move(cur), l, p->droptol[l], p->drop_schur, p->is_order, h->fb_min_ratio,
-                        next, h->err.rec.p, s);
+        factor_level<T>(f.lev[l], std::move(cur), l, p->droptol[l], p->drop_schur, p->is_order, p->group_rows,
+                        h->fb_min_ratio, next, h->err.rec.p, s);
         f.nlev = l + 1;
         ill_levels = check_dev_err(h, "factor");
         f.level_ms[l] = tm.stop();
@@ -220,7 +220,7 @@ int factor_impl(vbarms_t h, const vbarms_fparams *p, std::unique_ptr<Factors<T>>
         to_host(d, L.dlu_off.p + L.nis, 1, s);
         vals += d[0] + L.G.nv + L.W.nv;
         abytes += (double)sizeof(T) * (double)(d[0] + L.G.nv + L.W.nv) + 4.0 * (double)(L.G.nw + L.W.nw) +
-                  4.0 * L.n_is + 8.0 * 6.0 * L.n;
+                  4.0 * L.n_is + 4.0 * L.n + 8.0 * 6.0 * L.n;
     }
     f.apply_bytes = abytes;
     {
@@ -497,6 +497,7 @@ int vbarms_factor(vbarms_t h, const vbarms_fparams *p) {
         if (p->precision != VBARMS_F64 && p->precision != VBARMS_F32) fail(VBARMS_ERR_ARG, "invalid precision");
         if (p->is_order != VBARMS_IS_NATURAL && p->is_order != VBARMS_IS_WEIGHTED)
             fail(VBARMS_ERR_ARG, "invalid independent-set order");
+        if (p->group_rows < 0 || p->group_rows > VBARMS_MAX_BLOCK) fail(VBARMS_ERR_ARG, "invalid group_rows");
         if (!h->have_A) fail(VBARMS_ERR_STATE, "no compressed matrix: call vbarms_compress first");
         h->have_factors = false;
         h->err_level = h->err_block = -1;
@@ -819,7 +820,7 @@ int vbarms_level_info(vbarms_t h, int32_t level, int32_t *info) {
         need_factors(h);
         auto fill = [&](auto &f) {
             auto &L = level_of(f, level);
-            info[0] = L.p; info[1] = L.n; info[2] = L.nis; info[3] = L.n_is;
+            info[0] = L.p; info[1] = L.n; info[2] = L.nis; info[3] = L.n_is; info[4] = L.nis_sn;
         };
         if (h->precision == VBARMS_F32) fill(*h->f32); else fill(*h->f64);
         return VBARMS_OK;
@@ -831,9 +832,27 @@ int vbarms_level_is(vbarms_t h, int32_t level, int32_t *is_list) {
         need_factors(h);
         auto get = [&](auto &f) {
             auto &L = level_of(f, level);
+            if (!L.h_gptr.empty()) {
+                std::copy(L.h_members.begin(), L.h_members.end(), is_list);
+                return;
+            }
             std::vector<int> v;
             to_host(v, L.is_list.p, L.nis, h->stream);
             std::copy(v.begin(), v.end(), is_list);
+        };
+        if (h->precision == VBARMS_F32) get(*h->f32); else get(*h->f64);
+        return VBARMS_OK;
+    });
+}
+
+int vbarms_level_groups(vbarms_t h, int32_t level, int32_t *gptr) {
+    return guarded(h, [&] {
+        need_factors(h);
+        auto get = [&](auto &f) {
+            auto &L = level_of(f, level);
+            if (!L.h_gptr.empty()) std::copy(L.h_gptr.begin(), L.h_gptr.end(), gptr);
+            else
+                for (int g = 0; g <= L.nis; ++g) gptr[g] = g;
         };
         if (h->precision == VBARMS_F32) get(*h->f32); else get(*h->f64);
         return VBARMS_OK;

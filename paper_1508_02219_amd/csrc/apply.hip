@@ -1,6 +1,7 @@
 // The multilevel solve (Alg. 2) with the scalings and permutations of every level.
 //
-// At level l, with b_l in the level's numbering:
+// At level l, with b_l in the level's numbering (is_rows / rest_rows give the level row of
+// every row of the IS and rest numberings; a pivot block is one group of supernodes):
 //   f = (S1 b)_IS,  y_i = L_i^{-1} P_i f_i              one lane per pivot block
 //   g' = (S1 b)_rest - W y                             row-streamed SpMV with W
 //   z = next level (or the last-level block ILUT solve) on g'
@@ -15,24 +16,25 @@ namespace {
 constexpr int kTG = 8;
 
 template <class T>
-__global__ void k_lvl_down(int nis, const int *is_list, const int *rb, const int *is_rb, const double *s1,
-                           const double *b, const T *dlu, const int64_t *dlu_off, const int *dpiv, double *y) {
+__global__ void k_lvl_down(int nis, const int *is_rows, const int *is_rb, const double *s1, const double *b,
+                           const T *dlu, const int64_t *dlu_off, const int *dpiv, double *y) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nis) return;
-    int I = is_list[i];
-    int m = rb[I + 1] - rb[I];
+    const int m = is_rb[i + 1] - is_rb[i];
+    const int *rows = is_rows + is_rb[i];
     double x[VBARMS_MAX_BLOCK];
-    for (int r = 0; r < m; ++r) x[r] = s1[rb[I] + r] * b[rb[I] + r];
+    for (int r = 0; r < m; ++r) x[r] = s1[rows[r]] * b[rows[r]];
     dev_lu_fwd<T, double>(m, dlu + dlu_off[i], dpiv + is_rb[i], x);
     for (int r = 0; r < m; ++r) y[is_rb[i] + r] = x[r];
 }
 
-// out[rr] = scale * base[row(rr)] - sum_c P[rr, c] v[sc[c]], with row(rr) the level row of panel row rr
+// out[rr] = s1[row(rr)] base[row(rr)] - sum_c P[rr, c] v[sc[c]], with row(rr) = rows[rr]
+// the level row of panel row rr (rows == nullptr: out[rr] = base[rr] - ...)
 template <class T>
 __global__ void __launch_bounds__(256) k_lvl_spmv(int64_t nrows, const int *rowblk, const int *prb, const int64_t *wp,
                                                   const int64_t *vp, const int *sc, const T *pv, const double *v,
-                                                  const int *blk_list, const int *lrb, const double *s1,
-                                                  const double *base, double *out) {
+                                                  const int *rows, const double *s1, const double *base,
+                                                  double *out) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t rr = gid / kTG;
     int lane = (int)(gid % kTG);
@@ -49,9 +51,8 @@ __global__ void __launch_bounds__(256) k_lvl_spmv(int64_t nrows, const int *rowb
     for (int off = kTG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kTG);
     if (rr < nrows && lane == 0) {
         double bv;
-        if (blk_list) {
-            int J = blk_list[I];
-            int row = lrb[J] + (int)(rr - prb[I]);
+        if (rows) {
+            const int row = rows[rr];
             bv = s1[row] * base[row];
         } else {
             bv = base[rr];
@@ -61,24 +62,22 @@ __global__ void __launch_bounds__(256) k_lvl_spmv(int64_t nrows, const int *rowb
 }
 
 template <class T>
-__global__ void k_lvl_up(int nis, const int *is_list, const int *rb, const int *is_rb, const double *s2, const T *dlu,
+__global__ void k_lvl_up(int nis, const int *is_rows, const int *is_rb, const double *s2, const T *dlu,
                          const int64_t *dlu_off, const double *t, double *x) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nis) return;
-    int I = is_list[i];
-    int m = rb[I + 1] - rb[I];
+    const int m = is_rb[i + 1] - is_rb[i];
+    const int *rows = is_rows + is_rb[i];
     double u[VBARMS_MAX_BLOCK];
     for (int r = 0; r < m; ++r) u[r] = t[is_rb[i] + r];
     dev_lu_bwd<T, double>(m, dlu + dlu_off[i], u);
-    for (int r = 0; r < m; ++r) x[rb[I] + r] = s2[rb[I] + r] * u[r];
+    for (int r = 0; r < m; ++r) x[rows[r]] = s2[rows[r]] * u[r];
 }
 
-__global__ void k_lvl_rest_out(int64_t nrest_rows, const int *rest_rowblk, const int *rest_rb, const int *rest_list,
-                               const int *rb, const double *s2, const double *z, double *x) {
+__global__ void k_lvl_rest_out(int64_t nrest_rows, const int *rest_rows, const double *s2, const double *z, double *x) {
     int64_t rr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (rr >= nrest_rows) return;
-    int j = rest_rowblk[rr];
-    int row = rb[rest_list[j]] + (int)(rr - rest_rb[j]);
+    const int row = rest_rows[rr];
     x[row] = s2[row] * z[rr];
 }
 
@@ -91,35 +90,33 @@ void solve_levels(Factors<T> &f, int lvl, const double *b, double *x, int *err, 
         return;
     }
     Level<T> &L = f.lev[lvl];
-    const Panel<T> &As = L.As;
     if (!L.g.p) {
         L.g.alloc(std::max(L.n_rest, 1));
         L.z.alloc(std::max(L.n_rest, 1));
     }
     if (L.nis > 0) {
-        k_lvl_down<T><<<grid_for(L.nis, 64), 64, 0, s>>>(L.nis, L.is_list.p, As.rb.p, L.is_rb.p, L.s1.p, b, L.dlu.p,
+        k_lvl_down<T><<<grid_for(L.nis, 64), 64, 0, s>>>(L.nis, L.is_rows.p, L.is_rb.p, L.s1.p, b, L.dlu.p,
                                                           L.dlu_off.p, L.dpiv.p, L.y.p);
         VB_LAUNCH_CHECK();
     }
     if (L.n_rest > 0) {
         k_lvl_spmv<T><<<grid_for((int64_t)L.n_rest * kTG, 256), 256, 0, s>>>(
-            L.n_rest, L.W.rowblk.p, L.W.rb.p, L.W.wp.p, L.W.vp.p, L.W.sc.p, L.W.v.p, L.y.p, L.rest_list.p, As.rb.p,
-            L.s1.p, b, L.g.p);
+            L.n_rest, L.W.rowblk.p, L.W.rb.p, L.W.wp.p, L.W.vp.p, L.W.sc.p, L.W.v.p, L.y.p, L.rest_rows.p, L.s1.p, b,
+            L.g.p);
         VB_LAUNCH_CHECK();
     }
     solve_levels(f, lvl + 1, L.g.p, L.z.p, err, s);
     if (L.nis > 0) {
         k_lvl_spmv<T><<<grid_for((int64_t)L.n_is * kTG, 256), 256, 0, s>>>(L.n_is, L.G.rowblk.p, L.G.rb.p, L.G.wp.p,
                                                                              L.G.vp.p, L.G.sc.p, L.G.v.p, L.z.p,
-                                                                             nullptr, nullptr, nullptr, L.y.p, L.t.p);
+                                                                             nullptr, nullptr, L.y.p, L.t.p);
         VB_LAUNCH_CHECK();
-        k_lvl_up<T><<<grid_for(L.nis, 64), 64, 0, s>>>(L.nis, L.is_list.p, As.rb.p, L.is_rb.p, L.s2.p, L.dlu.p,
-                                                        L.dlu_off.p, L.t.p, x);
+        k_lvl_up<T><<<grid_for(L.nis, 64), 64, 0, s>>>(L.nis, L.is_rows.p, L.is_rb.p, L.s2.p, L.dlu.p, L.dlu_off.p,
+                                                        L.t.p, x);
         VB_LAUNCH_CHECK();
     }
     if (L.n_rest > 0) {
-        k_lvl_rest_out<<<grid_for(L.n_rest, 256), 256, 0, s>>>(L.n_rest, L.W.rowblk.p, L.rest_rb.p, L.rest_list.p,
-                                                               As.rb.p, L.s2.p, L.z.p, x);
+        k_lvl_rest_out<<<grid_for(L.n_rest, 256), 256, 0, s>>>(L.n_rest, L.rest_rows.p, L.s2.p, L.z.p, x);
         VB_LAUNCH_CHECK();
     }
 }

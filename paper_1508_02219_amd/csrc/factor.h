@@ -9,7 +9,8 @@ namespace vb {
 template <class T>
 struct Level {
     int p = 0, n = 0;             // supernodes / scalar size of A_l
-    int nis = 0, n_is = 0;        // independent-set supernodes / scalar size
+    int nis = 0, n_is = 0;        // pivot blocks of D (groups) / scalar size
+    int nis_sn = 0;               // supernodes in the groups
     int nrest = 0, n_rest = 0;    // remaining supernodes / scalar size
     Panel<T> A;                   // A_l as received (kept for inspection)
     Panel<T> As;                  // S1 A_l S2
@@ -19,6 +20,9 @@ struct Level {
     DBuf<int> is_list, rest_list; // ascending
     std::vector<int> h_is_rb, h_rest_rb;
     DBuf<int> is_rb, rest_rb;     // scalar offsets in the IS / rest numbering
+    DBuf<int> is_rows, rest_rows; // [n_is], [n_rest]: level row of every IS / rest row
+    std::vector<int> h_members;   // groups of several supernodes: members, group after group
+    std::vector<int> h_gptr;      // [nis+1] into h_members (empty with one supernode per group)
     DBuf<T> dlu;                  // LU of the IS pivot blocks, concatenated
     DBuf<int64_t> dlu_off;        // [nis+1]
     DBuf<int> dpiv;               // [n_is] local row interchanges
@@ -106,8 +110,8 @@ void panel_convert(const Panel<Tin> &src, Panel<Tout> &dst, hipStream_t s);
 // Pivot blocks whose pivot ratio (smallest over largest pivot magnitude) falls below
 // min_ratio are counted in err[3].
 template <class T>
-void factor_level(Level<T> &L, Panel<T> &&A, int lvl, double droptol, int drop_schur, int is_order, double min_ratio,
-                  Panel<T> &next, int *err, hipStream_t s);
+void factor_level(Level<T> &L, Panel<T> &&A, int lvl, double droptol, int drop_schur, int is_order, int group_rows,
+                  double min_ratio, Panel<T> &next, int *err, hipStream_t s);
 // Room reserved by the block ILUT, kept by the caller across factorizations: working rows
 // hold `grow` times their input row (and at least `grow` times the mean row); the L and U
 // pools hold `pool` times the input's blocks and values each; a row's block list in LDS

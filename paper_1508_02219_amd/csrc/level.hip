@@ -375,9 +375,243 @@ __global__ void k_is_weights(int p, const int *rb, const int64_t *rp, const int 
     w[I] = tot > 0.0 ? diag / tot : 0.0;
 }
 
+namespace {
+
+// ---- groups of supernodes (several supernodes per pivot block) ---------------------
+// Step 3 with groups: an unmarked supernode opens a group, its unmarked quotient-graph
+// neighbours (A + A^T) join in ascending order while the group keeps at most gmax rows
+// (one that does not fit is skipped), then the members and all their neighbours are
+// marked.  Every opening depends on all earlier marks, so the greedy is sequential by
+// definition; it runs on the host over a copy of the block pattern (p + nb integers).
+// Groups are numbered by their smallest supernode, members ascending.
+struct HostGroups {
+    int ng = 0;
+    std::vector<int> gid;            // [p] group, or -1
+    std::vector<int> gptr, members;  // members of group g: members[gptr[g] .. gptr[g+1])
+};
+
+HostGroups host_groups(int p, const std::vector<int64_t> &rp, const std::vector<int> &ci, const std::vector<int> &rb,
+                       int gmax, const std::vector<double> *wts) {
+    std::vector<int64_t> tp(p + 1, 0);
+    for (int c : ci) tp[c + 1]++;
+    for (int j = 0; j < p; ++j) tp[j + 1] += tp[j];
+    std::vector<int> tr(ci.size());
+    {
+        std::vector<int64_t> f(tp.begin(), tp.end() - 1);
+        for (int I = 0; I < p; ++I)
+            for (int64_t k = rp[I]; k < rp[I + 1]; ++k) tr[f[ci[k]]++] = I;
+    }
+    std::vector<int> order(p);
+    for (int I = 0; I < p; ++I) order[I] = I;
+    if (wts) std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return (*wts)[a] > (*wts)[b]; });
+    HostGroups G;
+    G.gid.assign(p, -1);
+    std::vector<char> marked(p, 0);
+    std::vector<int> nbr, mem;
+    for (int v : order) {
+        if (marked[v]) continue;
+        const int g = G.ng++;
+        int rows = rb[v + 1] - rb[v];
+        G.gid[v] = g;
+        marked[v] = 1;
+        mem.assign(1, v);
+        nbr.clear();
+        for (int64_t k = rp[v]; k < rp[v + 1]; ++k) nbr.push_back(ci[k]);
+        for (int64_t k = tp[v]; k < tp[v + 1]; ++k) nbr.push_back(tr[k]);
+        std::sort(nbr.begin(), nbr.end());
+        for (size_t a = 0; a < nbr.size(); ++a) {
+            const int u = nbr[a];
+            if (marked[u]) continue;
+            const int su = rb[u + 1] - rb[u];
+            if (rows + su > gmax) continue;
+            G.gid[u] = g;
+            marked[u] = 1;
+            mem.push_back(u);
+            rows += su;
+        }
+        for (int w : mem) {
+            for (int64_t k = rp[w]; k < rp[w + 1]; ++k) marked[ci[k]] = 1;
+            for (int64_t k = tp[w]; k < tp[w + 1]; ++k) marked[tr[k]] = 1;
+        }
+    }
+    std::vector<int> renum(G.ng, -1);
+    int seen = 0;
+    for (int I = 0; I < p; ++I)
+        if (G.gid[I] >= 0 && renum[G.gid[I]] < 0) renum[G.gid[I]] = seen++;
+    G.gptr.assign(G.ng + 1, 0);
+    for (int I = 0; I < p; ++I)
+        if (G.gid[I] >= 0) {
+            G.gid[I] = renum[G.gid[I]];
+            G.gptr[G.gid[I] + 1]++;
+        }
+    for (int g = 0; g < G.ng; ++g) G.gptr[g + 1] += G.gptr[g];
+    G.members.resize(G.gptr[G.ng]);
+    std::vector<int> fill(G.gptr.begin(), G.gptr.end() - 1);
+    for (int I = 0; I < p; ++I)
+        if (G.gid[I] >= 0) G.members[fill[G.gid[I]]++] = I;
+    return G;
+}
+
+// Upper bound of the distinct coarse block columns of every coarse block row.
+__global__ void k_rg_bound(int pc, const int *mptr, const int *mem, const int64_t *rp, int64_t *cnt) {
+    int X = blockIdx.x * blockDim.x + threadIdx.x;
+    if (X >= pc) return;
+    int64_t c = 0;
+    for (int a = mptr[X]; a < mptr[X + 1]; ++a) c += rp[mem[a] + 1] - rp[mem[a]];
+    cnt[X] = c;
+}
+// Coarse block columns of every coarse row: the members' block columns mapped to their
+// coarse blocks, sorted and deduplicated in place; cnt[X] = distinct count.
+__global__ void k_rg_cand(int pc, const int *mptr, const int *mem, const int64_t *rp, const int *ci, const int *cblk,
+                          const int64_t *off, int *cand, int64_t *cnt) {
+    int X = blockIdx.x * blockDim.x + threadIdx.x;
+    if (X >= pc) return;
+    int *c = cand + off[X];
+    int64_t k2 = 0;
+    for (int a = mptr[X]; a < mptr[X + 1]; ++a) {
+        const int I = mem[a];
+        for (int64_t k = rp[I]; k < rp[I + 1]; ++k) c[k2++] = cblk[ci[k]];
+    }
+    for (int64_t i = 1; i < k2; ++i) {  // insertion sort: the members' lists are sorted runs
+        const int v = c[i];
+        int64_t j = i - 1;
+        while (j >= 0 && c[j] > v) {
+            c[j + 1] = c[j];
+            --j;
+        }
+        c[j + 1] = v;
+    }
+    int64_t u = 0;
+    for (int64_t i = 0; i < k2; ++i)
+        if (u == 0 || c[i] != c[u - 1]) c[u++] = c[i];
+    cnt[X] = u;
+}
+__global__ void k_rg_cols(int pc, const int64_t *off, const int *cand, const int64_t *crp, int *cci) {
+    int X = blockIdx.x * blockDim.x + threadIdx.x;
+    if (X >= pc) return;
+    for (int64_t k = crp[X]; k < crp[X + 1]; ++k) cci[k] = cand[off[X] + (k - crp[X])];
+}
+// level row of every coarse row: crow[coarse row] = level row
+__global__ void k_rg_crow(int p, const int *rb, const int *cblk, const int *coff, const int *crb, int *crow) {
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= p) return;
+    const int base = crb[cblk[I]] + coff[I];
+    for (int r = 0; r < rb[I + 1] - rb[I]; ++r) crow[base + r] = rb[I] + r;
+}
+// Scatter of the level matrix into the coarse panel (zeroed beforehand), one thread per
+// level row: every block (I, J) lands in coarse block (cblk[I], cblk[J]) at row offset
+// coff[I] and column offset coff[J].
+template <class T>
+__global__ void k_rg_vals(int n, const int *rowblk, const int *rb, const int64_t *rp, const int *ci, const int *co,
+                          const int64_t *wp, const int64_t *vp, const T *v, const int *cblk, const int *coff,
+                          const int64_t *crp, const int *cci, const int *cco, const int64_t *cwp, const int64_t *cvp,
+                          T *cv, int *err) {
+    int fr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (fr >= n) return;
+    const int I = rowblk[fr];
+    const int r = fr - rb[I];
+    const int X = cblk[I];
+    const int64_t W = wp[I + 1] - wp[I], CW = cwp[X + 1] - cwp[X];
+    const T *src = v + vp[I] + r * W;
+    T *dst = cv + cvp[X] + (int64_t)(coff[I] + r) * CW;
+    for (int64_t k = rp[I]; k < rp[I + 1]; ++k) {
+        const int J = ci[k];
+        const int nJ = rb[J + 1] - rb[J];
+        const int64_t pos = dev_find(cci, crp[X], crp[X + 1], cblk[J]);
+        if (pos < 0) { dev_set_error(err, VBARMS_ERR_HIP, 2010, I); return; }
+        const int64_t dc = cco[pos] + coff[J];
+        for (int c = 0; c < nJ; ++c) dst[dc + c] = src[co[k] + c];
+    }
+}
+// level row of every row of a block list, in the list's own numbering (IS or rest)
+__global__ void k_row_maps(int nb, const int *list, const int *rb, const int *off, const int *crow, int *out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int I = list[i];
+    for (int r = 0; r < rb[I + 1] - rb[I]; ++r) out[off[i] + r] = crow ? crow[rb[I] + r] : rb[I] + r;
+}
+
+// The level matrix with every group merged into one block: coarse blocks 0 .. ng-1 are
+// the groups, then the remaining supernodes ascending.  crow receives the level row of
+// every coarse row.
+template <class T>
+void regroup_panel(const Panel<T> &A, const HostGroups &G, Panel<T> &Ac, DBuf<int> &crow, int *err, hipStream_t s) {
+    const int p = A.p;
+    const int n = A.h_rb.back();
+    std::vector<int> cblk(p), coff(p), mptr(1, 0), mem;
+    std::vector<int> crb(1, 0);
+    mem.reserve(p);
+    for (int g = 0; g < G.ng; ++g) {
+        int rows = 0;
+        for (int a = G.gptr[g]; a < G.gptr[g + 1]; ++a) {
+            const int I = G.members[a];
+            cblk[I] = g;
+            coff[I] = rows;
+            rows += A.h_rb[I + 1] - A.h_rb[I];
+            mem.push_back(I);
+        }
+        mptr.push_back((int)mem.size());
+        crb.push_back(crb.back() + rows);
+    }
+    int X = G.ng;
+    for (int I = 0; I < p; ++I) {
+        if (G.gid[I] >= 0) continue;
+        cblk[I] = X++;
+        coff[I] = 0;
+        mem.push_back(I);
+        mptr.push_back((int)mem.size());
+        crb.push_back(crb.back() + A.h_rb[I + 1] - A.h_rb[I]);
+    }
+    const int pc = X;
+    DBuf<int> d_cblk(std::max(p, 1)), d_coff(std::max(p, 1)), d_mptr(pc + 1), d_mem(std::max(p, 1));
+    to_device(d_cblk.p, cblk.data(), p, s);
+    to_device(d_coff.p, coff.data(), p, s);
+    to_device(d_mptr.p, mptr.data(), pc + 1, s);
+    to_device(d_mem.p, mem.data(), p, s);
+    panel_set_blocks(Ac, crb, crb, s);
+    Ac.rp.alloc(pc + 1);
+    {
+        DBuf<int64_t> bound(std::max(pc, 1)), off(pc + 1), cnt(std::max(pc, 1));
+        if (pc > 0) {
+            k_rg_bound<<<grid_for(pc, 256), 256, 0, s>>>(pc, d_mptr.p, d_mem.p, A.rp.p, bound.p);
+            VB_LAUNCH_CHECK();
+        }
+        const int64_t tot = scan_i64(bound.p, off.p, pc, s);
+        DBuf<int> cand(std::max<int64_t>(tot, 1));
+        if (pc > 0) {
+            k_rg_cand<<<grid_for(pc, 64), 64, 0, s>>>(pc, d_mptr.p, d_mem.p, A.rp.p, A.ci.p, d_cblk.p, off.p, cand.p,
+                                                       cnt.p);
+            VB_LAUNCH_CHECK();
+        }
+        Ac.nb = scan_i64(cnt.p, Ac.rp.p, pc, s);
+        Ac.ci.alloc(std::max<int64_t>(Ac.nb, 1));
+        if (pc > 0) {
+            k_rg_cols<<<grid_for(pc, 256), 256, 0, s>>>(pc, off.p, cand.p, Ac.rp.p, Ac.ci.p);
+            VB_LAUNCH_CHECK();
+        }
+        VB_HIP(hipStreamSynchronize(s));  // host vectors above are copy sources
+    }
+    panel_finish_layout(Ac, s);
+    Ac.v.alloc(std::max<int64_t>(Ac.nv, 1));
+    fill_val<T>(Ac.v.p, T(0), Ac.nv, s);
+    crow.alloc(std::max(n, 1));
+    if (p > 0) {
+        k_rg_crow<<<grid_for(p, 256), 256, 0, s>>>(p, A.rb.p, d_cblk.p, d_coff.p, Ac.rb.p, crow.p);
+        VB_LAUNCH_CHECK();
+    }
+    if (n > 0) {
+        k_rg_vals<T><<<grid_for(n, 128), 128, 0, s>>>(n, A.rowblk.p, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p,
+                                                       A.v.p, d_cblk.p, d_coff.p, Ac.rp.p, Ac.ci.p, Ac.co.p, Ac.wp.p,
+                                                       Ac.vp.p, Ac.v.p, err);
+        VB_LAUNCH_CHECK();
+    }
+}
+
+}  // namespace
+
 template <class T>
 void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop_schur, int is_order,
-                  double min_ratio, Panel<T> &next, int *err, hipStream_t s) {
+                  int group_rows, double min_ratio, Panel<T> &next, int *err, hipStream_t s) {
     L.A = std::move(Ain);
     const Panel<T> &A = L.A;
     L.p = A.p;
@@ -403,57 +637,84 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
         k_scale<T><<<g, 256, 0, s>>>(n, A.rowblk.p, A.rb.p, A.wp.p, A.vp.p, A.sc.p, A.v.p, L.s1.p, L.s2.p, L.As.v.p);
         VB_LAUNCH_CHECK();
     }
-    const Panel<T> &As = L.As;
+    // Step 3: block independent set on the quotient graph of A + A^T, in natural order or
+    // by descending weight; either one supernode per group (parallel LFMIS rounds) or
+    // groups of several supernodes merged into one block of a coarse copy of the matrix
+    const bool grouped = group_rows > 0;
+    Panel<T> Ac;       // grouped: the level matrix with every group as one block
+    DBuf<int> crow;    // grouped: level row of every row of Ac
+    HostGroups G;
+    DBuf<int> state;
+    {
+        const Panel<T> &As = L.As;
+        DBuf<double> wts;
+        if (is_order == 1 && p > 0) {
+            wts.alloc(p);
+            k_is_weights<T><<<grid_for(p, 256), 256, 0, s>>>(p, As.rb.p, As.rp.p, As.ci.p, As.co.p, As.wp.p, As.vp.p,
+                                                             As.v.p, wts.p);
+            VB_LAUNCH_CHECK();
+        }
+        if (grouped) {
+            std::vector<int64_t> hrp;
+            std::vector<int> hci;
+            std::vector<double> hw;
+            to_host(hrp, As.rp.p, p + 1, s);
+            to_host(hci, As.ci.p, As.nb, s);
+            if (is_order == 1) to_host(hw, wts.p, p, s);
+            G = host_groups(p, hrp, hci, As.h_rb, group_rows, is_order == 1 ? &hw : nullptr);
+            regroup_panel(As, G, Ac, crow, err, s);
+            state.alloc(std::max(Ac.p, 1));
+            fill_i32(state.p, 1, G.ng, s);
+            fill_i32(state.p + G.ng, 2, Ac.p - G.ng, s);
+            L.h_members = G.members;
+            L.h_gptr = G.gptr;
+        } else {
+            state.alloc(std::max(p, 1));
+            DBuf<int> tcnt(std::max(p, 1)), tfill(std::max(p, 1));
+            DBuf<int64_t> tptr(p + 1);
+            fill_i32(tcnt.p, 0, p, s);
+            fill_i32(tfill.p, 0, p, s);
+            if (p > 0) {
+                k_tcount<<<grid_for(p, 256), 256, 0, s>>>(p, As.rp.p, As.ci.p, tcnt.p);
+                VB_LAUNCH_CHECK();
+            }
+            int64_t nt = scan_i32_to_i64(tcnt.p, tptr.p, p, s);
+            DBuf<int> tlist(std::max<int64_t>(nt, 1));
+            if (p > 0) {
+                k_tfill<<<grid_for(p, 256), 256, 0, s>>>(p, As.rp.p, As.ci.p, tptr.p, tfill.p, tlist.p);
+                VB_LAUNCH_CHECK();
+            }
+            lfmis(p, As.rp.p, As.ci.p, tptr.p, tlist.p, wts.p, state.p, s);
+            L.h_members.clear();
+            L.h_gptr.clear();
+        }
+    }
+    // from here on the working matrix: the scaled level matrix, or its grouped copy
+    const Panel<T> &As = grouped ? Ac : L.As;
+    const int pw = As.p;
 
-    // Step 3: independent set on the quotient graph of A + A^T, in natural order or by
-    // descending weight
-    DBuf<int> state(std::max(p, 1));
-    DBuf<double> wts;
-    if (is_order == 1 && p > 0) {
-        wts.alloc(p);
-        k_is_weights<T><<<grid_for(p, 256), 256, 0, s>>>(p, As.rb.p, As.rp.p, As.ci.p, As.co.p, As.wp.p, As.vp.p,
-                                                         As.v.p, wts.p);
-        VB_LAUNCH_CHECK();
-    }
-    {
-        DBuf<int> tcnt(std::max(p, 1)), tfill(std::max(p, 1));
-        DBuf<int64_t> tptr(p + 1);
-        fill_i32(tcnt.p, 0, p, s);
-        fill_i32(tfill.p, 0, p, s);
-        if (p > 0) {
-            k_tcount<<<grid_for(p, 256), 256, 0, s>>>(p, As.rp.p, As.ci.p, tcnt.p);
-            VB_LAUNCH_CHECK();
-        }
-        int64_t nt = scan_i32_to_i64(tcnt.p, tptr.p, p, s);
-        DBuf<int> tlist(std::max<int64_t>(nt, 1));
-        if (p > 0) {
-            k_tfill<<<grid_for(p, 256), 256, 0, s>>>(p, As.rp.p, As.ci.p, tptr.p, tfill.p, tlist.p);
-            VB_LAUNCH_CHECK();
-        }
-        lfmis(p, As.rp.p, As.ci.p, tptr.p, tlist.p, wts.p, state.p, s);
-    }
     // P_I: independent blocks ascending, then the rest ascending
-    L.is_flag.alloc(std::max(p, 1));
-    L.num.alloc(std::max(p, 1));
+    L.is_flag.alloc(std::max(pw, 1));
+    L.num.alloc(std::max(pw, 1));
     {
-        DBuf<int> restf(std::max(p, 1)), issz(std::max(p, 1)), restsz(std::max(p, 1));
-        DBuf<int> isidx(p + 1), restidx(p + 1), isoff(p + 1), restoff(p + 1);
-        if (p > 0) {
-            k_is_flags<<<grid_for(p, 256), 256, 0, s>>>(p, state.p, As.rb.p, L.is_flag.p, restf.p, issz.p, restsz.p);
+        DBuf<int> restf(std::max(pw, 1)), issz(std::max(pw, 1)), restsz(std::max(pw, 1));
+        DBuf<int> isidx(pw + 1), restidx(pw + 1), isoff(pw + 1), restoff(pw + 1);
+        if (pw > 0) {
+            k_is_flags<<<grid_for(pw, 256), 256, 0, s>>>(pw, state.p, As.rb.p, L.is_flag.p, restf.p, issz.p, restsz.p);
             VB_LAUNCH_CHECK();
         }
-        L.nis = scan_i32(L.is_flag.p, isidx.p, p, s);
-        L.nrest = p - L.nis;
-        scan_i32(restf.p, restidx.p, p, s, false);
-        L.n_is = scan_i32(issz.p, isoff.p, p, s);
+        L.nis = scan_i32(L.is_flag.p, isidx.p, pw, s);
+        L.nrest = pw - L.nis;
+        scan_i32(restf.p, restidx.p, pw, s, false);
+        L.n_is = scan_i32(issz.p, isoff.p, pw, s);
         L.n_rest = n - L.n_is;
-        scan_i32(restsz.p, restoff.p, p, s, false);
+        scan_i32(restsz.p, restoff.p, pw, s, false);
         L.is_list.alloc(std::max(L.nis, 1));
         L.rest_list.alloc(std::max(L.nrest, 1));
         L.is_rb.alloc(L.nis + 1);
         L.rest_rb.alloc(L.nrest + 1);
-        if (p > 0) {
-            k_numbering<<<grid_for(p, 256), 256, 0, s>>>(p, L.is_flag.p, isidx.p, restidx.p, isoff.p, restoff.p,
+        if (pw > 0) {
+            k_numbering<<<grid_for(pw, 256), 256, 0, s>>>(pw, L.is_flag.p, isidx.p, restidx.p, isoff.p, restoff.p,
                                                           L.num.p, L.is_list.p, L.rest_list.p, L.is_rb.p, L.rest_rb.p);
             VB_LAUNCH_CHECK();
         }
@@ -461,6 +722,19 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
         VB_HIP(hipMemcpyAsync(L.rest_rb.p + L.nrest, &L.n_rest, sizeof(int), hipMemcpyHostToDevice, s));
         to_host(L.h_is_rb, L.is_rb.p, L.nis + 1, s);
         to_host(L.h_rest_rb, L.rest_rb.p, L.nrest + 1, s);
+    }
+    L.nis_sn = grouped ? (int)G.members.size() : L.nis;
+    L.is_rows.alloc(std::max(L.n_is, 1));
+    L.rest_rows.alloc(std::max(L.n_rest, 1));
+    if (L.nis > 0) {
+        k_row_maps<<<grid_for(L.nis, 256), 256, 0, s>>>(L.nis, L.is_list.p, As.rb.p, L.is_rb.p,
+                                                         grouped ? crow.p : nullptr, L.is_rows.p);
+        VB_LAUNCH_CHECK();
+    }
+    if (L.nrest > 0) {
+        k_row_maps<<<grid_for(L.nrest, 256), 256, 0, s>>>(L.nrest, L.rest_list.p, As.rb.p, L.rest_rb.p,
+                                                           grouped ? crow.p : nullptr, L.rest_rows.p);
+        VB_LAUNCH_CHECK();
     }
     const int nis = L.nis, nrest = L.nrest;
 
@@ -482,30 +756,42 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
                                                       err);
             VB_LAUNCH_CHECK();
         }
-        if (read_one(err, s) != 0) return;
+        if (read_one(err, s) != 0) {
+            if (grouped) {  // report the group's smallest supernode, as in the level numbering
+                int rec[3];
+                VB_HIP(hipMemcpyAsync(rec, err, sizeof(rec), hipMemcpyDeviceToHost, s));
+                VB_HIP(hipStreamSynchronize(s));
+                if (rec[0] == VBARMS_ERR_SINGULAR && rec[2] >= 0 && rec[2] < G.ng) {
+                    rec[2] = G.members[G.gptr[rec[2]]];
+                    VB_HIP(hipMemcpyAsync(err + 2, rec + 2, sizeof(int), hipMemcpyHostToDevice, s));
+                    VB_HIP(hipStreamSynchronize(s));
+                }
+            }
+            return;
+        }
     }
 
     // G = L^{-1} P F and W = E U^{-1} into one scratch copy (their blocks are disjoint)
     DBuf<T> tmp(std::max<int64_t>(As.nv, 1));
     DBuf<int> keep(std::max<int64_t>(As.nb, 1));
     if (As.nw > 0) {
-        k_compute_g<T><<<grid_for(As.nw, 128), 128, 0, s>>>(p, As.nw, As.wp.p, As.vp.p, As.rb.p, As.sc.p,
+        k_compute_g<T><<<grid_for(As.nw, 128), 128, 0, s>>>(pw, As.nw, As.wp.p, As.vp.p, As.rb.p, As.sc.p,
                                                              As.rowblk.p, L.is_flag.p, L.num.p, As.v.p, L.dlu.p,
                                                              L.dlu_off.p, L.dpiv.p, L.is_rb.p, tmp.p);
         VB_LAUNCH_CHECK();
-        k_compute_w<T><<<grid_for(As.nb * As.maxm, 128), 128, 0, s>>>(p, As.nb, As.maxm, As.rp.p, As.ci.p, As.co.p,
+        k_compute_w<T><<<grid_for(As.nb * As.maxm, 128), 128, 0, s>>>(pw, As.nb, As.maxm, As.rp.p, As.ci.p, As.co.p,
                                                                        As.wp.p, As.vp.p, As.rb.p, L.is_flag.p,
                                                                        L.num.p, As.v.p, L.dlu.p, L.dlu_off.p, tmp.p);
         VB_LAUNCH_CHECK();
     }
     if (As.nb > 0) {
-        k_keep_gw<T><<<grid_for(As.nb, 256), 256, 0, s>>>(p, As.nb, As.rp.p, As.ci.p, As.co.p, As.wp.p, As.vp.p,
+        k_keep_gw<T><<<grid_for(As.nb, 256), 256, 0, s>>>(pw, As.nb, As.rp.p, As.ci.p, As.co.p, As.wp.p, As.vp.p,
                                                            As.rb.p, L.is_flag.p, tmp.p, droptol, 0, keep.p);
         VB_LAUNCH_CHECK();
     }
     panel_compact<T>(As, tmp.p, keep.p, L.is_list.p, nis, L.num.p, L.h_is_rb, L.h_rest_rb, L.G, s);
     if (As.nb > 0) {
-        k_keep_gw<T><<<grid_for(As.nb, 256), 256, 0, s>>>(p, As.nb, As.rp.p, As.ci.p, As.co.p, As.wp.p, As.vp.p,
+        k_keep_gw<T><<<grid_for(As.nb, 256), 256, 0, s>>>(pw, As.nb, As.rp.p, As.ci.p, As.co.p, As.wp.p, As.vp.p,
                                                            As.rb.p, L.is_flag.p, tmp.p, droptol, 1, keep.p);
         VB_LAUNCH_CHECK();
     }
@@ -554,9 +840,9 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
     L.t.alloc(std::max(L.n_is, 1));
 }
 
-template void factor_level<double>(Level<double> &, Panel<double> &&, int, double, int, int, double, Panel<double> &,
-                                   int *, hipStream_t);
-template void factor_level<float>(Level<float> &, Panel<float> &&, int, double, int, int, double, Panel<float> &, int *,
-                                  hipStream_t);
+template void factor_level<double>(Level<double> &, Panel<double> &&, int, double, int, int, int, double,
+                                   Panel<double> &, int *, hipStream_t);
+template void factor_level<float>(Level<float> &, Panel<float> &&, int, double, int, int, int, double, Panel<float> &,
+                                  int *, hipStream_t);
 
 }  // namespace vb

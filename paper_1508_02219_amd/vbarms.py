@@ -52,7 +52,7 @@ class CStats(C.Structure):
 
 class _FParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("droptol", C.c_double * (MAX_LEVELS + 1)), ("drop_schur", C.c_int32),
-                ("is_order", C.c_int32), ("precision", C.c_int32)]
+                ("is_order", C.c_int32), ("precision", C.c_int32), ("group_rows", C.c_int32)]
 
 
 class SInfo(C.Structure):
@@ -113,6 +113,7 @@ SIGNATURES = {
     "vbarms_num_levels": (C.c_int, [_P, _P]),
     "vbarms_level_info": (C.c_int, [_P, C.c_int32, _P]),
     "vbarms_level_is": (C.c_int, [_P, C.c_int32, _P]),
+    "vbarms_level_groups": (C.c_int, [_P, C.c_int32, _P]),
     "vbarms_level_scaling": (C.c_int, [_P, C.c_int32, _P, _P]),
     "vbarms_matrix_dims": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
     "vbarms_matrix_get": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P]),
@@ -254,17 +255,8 @@ class Solver:
         return st
 
     # -- Steps 2-4 and the last level ---------------------------------------------------
-    def factor(self, levels, droptol, drop_schur=1, precision=F64, is_order=IS_NATURAL):
-        p = _FParams()
-        p.levels = levels
-        dt = np.asarray(droptol, dtype=np.float64).ravel()
-        if dt.size == 1:
-            dt = np.full(levels + 1, dt[0])
-        for i in range(levels + 1):
-            p.droptol[i] = float(dt[i])
-        p.drop_schur = drop_schur
-        p.is_order = is_order
-        p.precision = precision
+    def factor(self, levels, droptol, drop_schur=1, precision=F64, is_order=IS_NATURAL, group_rows=0):
+        p = _fparams(levels, droptol, drop_schur, precision, is_order, group_rows)
         self._check(lib().vbarms_factor(self.h, C.byref(p)))
 
     def error_location(self):
@@ -338,15 +330,21 @@ class Solver:
         return v.value
 
     def level_info(self, level):
-        info = np.zeros(4, np.int32)
+        info = np.zeros(5, np.int32)
         self._check(lib().vbarms_level_info(self.h, level, _np_ptr(info)))
-        return dict(p=int(info[0]), n=int(info[1]), nis=int(info[2]), n_is=int(info[3]))
+        return dict(p=int(info[0]), n=int(info[1]), nis=int(info[2]), n_is=int(info[3]), nis_sn=int(info[4]))
 
     def level_is(self, level):
-        k = self.level_info(level)["nis"]
+        k = self.level_info(level)["nis_sn"]
         out = np.zeros(max(k, 1), np.int32)
         self._check(lib().vbarms_level_is(self.h, level, _np_ptr(out)))
         return out[:k]
+
+    def level_groups(self, level):
+        k = self.level_info(level)["nis"]
+        out = np.zeros(k + 1, np.int32)
+        self._check(lib().vbarms_level_groups(self.h, level, _np_ptr(out)))
+        return out
 
     def level_scaling(self, level):
         n = self.level_info(level)["n"]
@@ -371,7 +369,7 @@ class Solver:
         return Exported(rb, cb, rowptr, colidx[:nb], vals[:nv], piv)
 
 
-def _fparams(levels, droptol, drop_schur=1, precision=F64, is_order=IS_NATURAL):
+def _fparams(levels, droptol, drop_schur=1, precision=F64, is_order=IS_NATURAL, group_rows=0):
     p = _FParams()
     p.levels = levels
     dt = np.asarray(droptol, dtype=np.float64).ravel()
@@ -382,6 +380,7 @@ def _fparams(levels, droptol, drop_schur=1, precision=F64, is_order=IS_NATURAL):
     p.drop_schur = drop_schur
     p.is_order = is_order
     p.precision = precision
+    p.group_rows = group_rows
     return p
 
 
@@ -418,7 +417,7 @@ class BatchSolver:
         msg = lib().vbarms_batch_last_error(self.b)
         raise VbarmsError(rc, msg.decode() if msg else "")
 
-    def factor(self, systems, tau, levels, droptol, drop_schur=1, precision=F64, is_order=IS_NATURAL):
+    def factor(self, systems, tau, levels, droptol, drop_schur=1, precision=F64, is_order=IS_NATURAL, group_rows=0):
         """systems: list of (rowptr, col, val) device tensors."""
         torch = self._torch
         descs = (_Csr * len(systems))()
@@ -426,7 +425,7 @@ class BatchSolver:
         for q, (rp, ci, va) in enumerate(systems):
             descs[q] = _Csr(rp.numel() - 1, int(ci.numel()), _dev_ptr(rp, torch.int64), _dev_ptr(ci, torch.int32),
                             _dev_ptr(va, torch.float64))
-        p = _fparams(levels, droptol, drop_schur, precision, is_order)
+        p = _fparams(levels, droptol, drop_schur, precision, is_order, group_rows)
         self._check(lib().vbarms_batch_factor(self.b, len(systems), descs, float(tau), C.byref(p)))
         off = np.zeros(len(systems) + 1, np.int64)
         self._check(lib().vbarms_batch_offsets(self.b, _np_ptr(off)))

@@ -31,7 +31,8 @@ def _no_diagonal(seed):
     n = s.n
     rows = np.repeat(np.arange(n), np.diff(s.rowptr))
     keep = rows != s.col
-    return synth._csr_from_coo(n, rows[keep], s.col[keep], s.val[keep])
+    rp, ci, va = synth._csr_from_coo(n, rows[keep], s.col[keep], s.val[keep])
+    return synth.System(n, rp, ci, va, np.zeros(n), np.ones(n, np.int32), name=f"nodiag-{seed}")
 
 
 INPUTS = {

@@ -14,8 +14,8 @@ log10 t_L].  Without a trained network the defaults tau = 0.7 and t = 1e-4 apply
 
 ``python -m paper_1508_02219_amd.learned --out FILE`` labels the training set on the GPU
 (the recipe of the learned-selection workload: upwind grids of 20^3 to 34^3 nodes, a
-fixed block size of 4, 5 or 6 per matrix, Peclet LogUniform(0.1, 1000), z-link
-anisotropy 1..100, 0-20% block perturbation) and writes it as JSON.
+fixed block size of 4, 5 or 6 per matrix, a cell Peclet number LogUniform(0.1, 1000) per
+matrix, z-link anisotropy 1..100, 0-20% block perturbation) and writes it as JSON.
 """
 from __future__ import annotations
 
@@ -31,11 +31,14 @@ import numpy as np
 from . import synth
 from . import vbarms as V
 
-TAUS = (0.6, 0.7, 0.8, 0.9, 1.0)
-TOLS = (1e-5, 1e-4, 1e-3, 1e-2)
+# The sweep grid: on the training distribution no other tau of 0.6 .. 1.0 came within 15%
+# of a matrix's best time; t = 1e-4 is rarely fastest but is the only setting that
+# converges on some high-Peclet matrices.
+TAUS = (0.7, 0.8, 0.9)
+TOLS = (1e-4, 1e-3, 1e-2, 1e-1)
 DEFAULT_TAU, DEFAULT_TOL = 0.7, 1e-4
 LEVELS = 3
-RESTART, RTOL, MAXIT = 50, 1e-8, 400
+RESTART, RTOL, MAXIT = 50, 1e-8, 120
 HIDDEN, DEPTH = 128, 3
 FAIL_RATIO = 10.0  # a setting that does not converge counts as 10x the best time
 
@@ -50,16 +53,22 @@ class RunResult:
     relres: float
 
 
-def recipe(seed: int, side_range=(20, 34)):
-    """Parameters of one matrix of the training distribution (seeded)."""
+SIDES = (20, 34)
+
+
+def recipe(seed: int, side_range=SIDES):
+    """Parameters of one matrix of the training distribution (seeded): the matrix's cell
+    Peclet number is LogUniform(0.1, 1000) and its nodes vary by a factor of two around it."""
     rng = np.random.default_rng(10_000 + seed)
     return dict(side=int(rng.integers(side_range[0], side_range[1] + 1)), ell=int(rng.choice([4, 5, 6])),
+                pe=float(np.exp(rng.uniform(np.log(0.1), np.log(1000.0)))),
                 aniso=float(np.exp(rng.uniform(0.0, np.log(100.0)))), pert=float(rng.uniform(0.0, 0.2)),
                 seed=int(seed))
 
 
-def make_system(r):
-    return synth.upwind_system(r["side"], r["side"], r["side"], ell_choices=(r["ell"],), pe_range=(0.1, 1000.0),
+def make_system(r, side=None):
+    side = side or r["side"]
+    return synth.upwind_system(side, side, side, ell_choices=(r["ell"],), pe_range=(r["pe"] / 2, r["pe"] * 2),
                                anisotropy=r["aniso"], perturb=r["pert"], seed=r["seed"])
 
 
@@ -76,7 +85,7 @@ def run_once(sv: V.Solver, dev, b, tau, tols, levels=LEVELS, restart=RESTART, rt
     return RunResult(tau, tols, ok, info.iters, st.compress_ms + st.factor_ms + st.solve_ms, info.true_relres)
 
 
-def run_median(sv, dev, b, tau, tols, repeats=3, **kw) -> RunResult:
+def run_median(sv, dev, b, tau, tols, repeats=1, **kw) -> RunResult:
     """The run with the median time of `repeats` identical runs (results are deterministic)."""
     runs = sorted((run_once(sv, dev, b, tau, tols, **kw) for _ in range(repeats)), key=lambda r: r.ms)
     return runs[len(runs) // 2]
@@ -183,7 +192,7 @@ class Predictor:
         return out
 
 
-def build_dataset(count, out, side_range=(20, 34), first_seed=0):
+def build_dataset(count, out, side_range=SIDES, first_seed=0):
     """Labels `count` training matrices and writes them as JSON (one record per matrix)."""
     recs = []
     t0 = time.time()
@@ -194,7 +203,8 @@ def build_dataset(count, out, side_range=(20, 34), first_seed=0):
         rec = dict(recipe=r, n=s.n, nnz=s.nnz, features=[float(x) for x in feats],
                    grid=[[g.tau, g.tols[0], bool(g.ok), g.ms if g.ok else None, g.iters] for g in grid], label=lab)
         recs.append(rec)
-        print(f"[learned] {k}: n={s.n} side={r['side']} ell={r['ell']} pert={r['pert']:.3f} aniso={r['aniso']:.1f} "
+        print(f"[learned] {k}: n={s.n} side={r['side']} ell={r['ell']} pe={r['pe']:.2f} pert={r['pert']:.3f} "
+              f"aniso={r['aniso']:.1f} "
               f"label={lab} ({time.time() - t0:.0f} s)", flush=True)
         with open(out, "w") as f:
             json.dump(dict(levels=LEVELS, taus=TAUS, tols=TOLS, restart=RESTART, rtol=RTOL, maxit=MAXIT,
@@ -202,14 +212,18 @@ def build_dataset(count, out, side_range=(20, 34), first_seed=0):
     return recs
 
 
-def load_dataset(path):
+def load_dataset(path, taus=TAUS, tols=TOLS):
+    """Labelled records with their grids restricted to (taus x tols)."""
     with open(path) as f:
         d = json.load(f)
     recs = [r for r in d["records"] if r["label"] is not None]
+    keep = {(a, b) for a in taus for b in tols}
     for r in recs:
+        r["grid"] = [g for g in r["grid"] if (g[0], g[1]) in keep]
         for g in r["grid"]:
             if g[3] is None:
                 g[3] = math.inf
+    recs = [r for r in recs if len(r["grid"]) == len(keep) and any(g[2] for g in r["grid"])]
     return d, recs
 
 

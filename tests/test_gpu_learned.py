@@ -1,10 +1,13 @@
 """GPU checks of the learned parameter selection: MLP kernels and features against the
 FP64 references, and what a network trained on the method's own sweeps gains over the
 default parameters on held-out matrices."""
+import os
 import sys
 
 import numpy as np
 import pytest
+
+from tests.conftest import ROOT
 
 from oracle import mlp_oracle as M
 from paper_1508_02219_amd import synth
@@ -81,36 +84,72 @@ def test_features_match_reference(vb, make):
     assert np.allclose(f, fo, rtol=1e-5, atol=1e-6), (f, fo)
 
 
-def test_learned_parameters_gain_over_defaults(vb):
-    """Trains on sweeps the method runs and compares, on held-out matrices, the measured
-    time-to-solve at the predicted parameters with the time at the defaults."""
+DATA = os.path.join(ROOT, "paper_1508_02219_amd", "data", "x4_training_sweeps.json")
+
+
+def _measure(Lr, vb, s, tau, tols, repeats=3):
+    """Measured time-to-solve (ms) of the method at (tau, tols) on s: the median of
+    `repeats` runs after a warm-up, or the warm-up run alone when it does not converge
+    (results are deterministic, so a failing setting fails every time)."""
+    import torch
+    sv = vb.Solver()
+    dev = vb.csr_to_device(s)
+    b = torch.as_tensor(s.b, device="cuda")
+    r = Lr.run_once(sv, dev, b, tau, tols)
+    if r.ok:
+        r = Lr.run_median(sv, dev, b, tau, tols, repeats=repeats)
+    sv.close()
+    return r
+
+
+def test_learned_parameters_gain_over_defaults_and_best_constant(vb):
+    """Trains the network (library kernels) on the stored sweeps of 100 training matrices,
+    then on held-out matrices larger than any training matrix measures the time-to-solve at
+    the learned strategy (predicted tau and per-level t; the defaults when FGMRES does not
+    converge with them, as the method prescribes), the defaults, and the best constant
+    setting of the training sweeps with the same fallback, under the iteration limit of the
+    sweeps.  A strategy that falls back is charged both runs.  A matrix the defaults do not
+    solve ranks nothing and is only reported.  The learned strategy must beat the defaults
+    by 2x and the best constant."""
     from paper_1508_02219_amd import learned as Lr
-    levels = 3
-    taus, tols = (0.7, 0.8, 0.9, 1.0), (1e-4, 1e-3, 1e-2)
-    train, test = [], []
-    for k in range(14):
-        s = Lr.training_system(k, side_range=(5, 8))
-        f, res = Lr.sweep(s, levels=levels, taus=taus, tols=tols)
-        (test if k >= 10 else train).append((s, f, res))
-        _say(f"[case] sweep {k} {s.name} n={s.n}: best "
-             f"{min((r for r in res if r.ok), key=lambda r: r.ms).__dict__ if any(r.ok for r in res) else None}")
-    X = np.array([f for _, f, _ in train])
-    Y = np.array([Lr.label(res, levels) for _, _, res in train])
-    pred = Lr.Predictor(levels=levels, seed=0)
-    losses = pred.fit(X, Y, epochs=300, lr=3e-3, batch=16)
-    assert losses[-1] < losses[0]
-    ratios = []
-    for s, f, res in test:
-        (tau, tl), = pred.predict(f)
-        # snap the prediction to the sweep grid and read the measured time there
-        tau_g = min(taus, key=lambda v: abs(v - tau))
-        t_g = min(tols, key=lambda v: abs(np.log10(v) - np.log10(tl[-1])))
-        at = {(r.tau, r.tol): r for r in res}
-        got, dflt = at[(tau_g, t_g)], at[(Lr.DEFAULT_TAU, Lr.DEFAULT_TOL)]
-        assert got.ok, f"predicted ({tau_g}, {t_g}) did not converge on {s.name}"
-        ratios.append(got.ms / dflt.ms if dflt.ok else 0.0)
-        _say(f"[case] held-out {s.name}: predicted ({tau_g}, {t_g}) {got.ms:.2f} ms, "
-             f"default {dflt.ms if dflt.ok else float('inf'):.2f} ms")
-    gain = 1.0 / np.exp(np.mean(np.log(np.maximum(ratios, 1e-3))))
-    _say(f"[case] learned parameters: geometric-mean speedup over the defaults {gain:.2f}x")
-    assert gain >= 0.95
+    meta, recs = Lr.load_dataset(DATA)
+    assert len(recs) >= 90
+    X = np.array([r["features"] for r in recs], np.float32)
+    Y = np.array([Lr.target(r["label"]) for r in recs], np.float32)
+    pred = Lr.Predictor(seed=0)
+    losses = pred.fit(X, Y, epochs=200, lr=2e-3, batch=32)
+    assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:10])
+    (ctau, ctol), cscore = Lr.best_constant(recs)
+    _say(f"[case] best constant setting of the training sweeps: tau={ctau} t={ctol} "
+         f"(geometric mean {cscore:.2f}x of each matrix's best grid time)")
+    gains_c, gains_d, unsolved = [], [], 0
+    for k in range(10):
+        r = Lr.recipe(5000 + k, side_range=(34, 34))
+        s = Lr.make_system(r)
+        sv = vb.Solver()
+        feats = sv.features(*vb.csr_to_device(s))
+        sv.close()
+        (tau, tols), = pred.predict(feats)
+        got = _measure(Lr, vb, s, tau, tols)
+        const = _measure(Lr, vb, s, ctau, ctol)
+        dflt = _measure(Lr, vb, s, Lr.DEFAULT_TAU, Lr.DEFAULT_TOL)
+        desc = (f"[case] held-out {s.name} n={s.n} pe={r['pe']:.2f} aniso={r['aniso']:.1f} pert={r['pert']:.3f}: "
+                f"predicted tau={tau:.3f} t={[f'{v:.1e}' for v in tols]}")
+        if not dflt.ok:
+            unsolved += 1
+            _say(desc + ": the defaults do not converge within the iteration limit either")
+            continue
+        t_learned = got.ms if got.ok else got.ms + dflt.ms
+        t_const = const.ms if const.ok else const.ms + dflt.ms
+        gains_c.append(t_const / t_learned)
+        gains_d.append(dflt.ms / t_learned)
+        _say(desc + f" {t_learned:.1f} ms ({got.iters} its{'' if got.ok else ', then the defaults'}); constant "
+             f"{t_const:.1f} ms ({const.iters} its{'' if const.ok else ', then the defaults'}); defaults "
+             f"{dflt.ms:.1f} ms ({dflt.iters} its)")
+    assert len(gains_c) >= 6, f"only {len(gains_c)} held-out matrices were solvable"
+    gc = float(np.exp(np.mean(np.log(gains_c))))
+    gd = float(np.exp(np.mean(np.log(gains_d))))
+    _say(f"[case] learned parameters on {len(gains_c)} held-out matrices ({unsolved} unsolved by the defaults): "
+         f"geometric-mean speedup {gc:.3f}x over the best constant, {gd:.2f}x over the defaults")
+    assert gd >= 2.0
+    assert gc > 1.0

@@ -4,7 +4,8 @@
 Default workload: 74^3 mesh nodes (405,224) on the 14-neighbour random stencil, a block of
 1 to 7 unknowns per node drawn uniformly (n = 1,619,907, nnz = 96.6M), upwind convection
 values with cell Peclet numbers LogUniform(0.1, 100); tau = 1 (exact node blocks), 4
-levels, drop tolerance 1e-4, FGMRES(60) to a true relative residual of 1e-8, b = A 1.
+levels whose independent sets are groups of supernodes of up to 32 rows, drop tolerance
+1e-4, FGMRES(60) to a true relative residual of 1e-8, b = A 1.
 `--workload grid40` runs the 40^3 five-unknown workload instead (n = 320,000, 10% block
 perturbation, tau = 0.8, 3 levels, FGMRES(50)).
 
@@ -41,11 +42,11 @@ WORKLOADS = {
                           "convection (cell Peclet LogUniform(0.1, 100))",
                      make=lambda side: __import__("paper_1508_02219_amd.synth", fromlist=["x"]).upwind_system(
                          side, side, side, seed=3),
-                     side=74, sample_side=48, tau=1.0, levels=4, droptol=1e-4, restart=60),
+                     side=74, sample_side=48, tau=1.0, levels=4, droptol=1e-4, restart=60, group_rows=32),
     "grid40": dict(desc="40^3 nodes, 14-neighbour random stencil, 5 unknowns per node, 10% block perturbation",
                    make=lambda side: __import__("paper_1508_02219_amd.synth", fromlist=["x"]).grid_system(
                        side, side, side, 5, "14rand", 0.10, seed=2),
-                   side=40, sample_side=40, tau=0.8, levels=3, droptol=1e-4, restart=50),
+                   side=40, sample_side=40, tau=0.8, levels=3, droptol=1e-4, restart=50, group_rows=0),
 }
 
 
@@ -70,7 +71,8 @@ def _cpu_baseline(wl, n_full):
     system = wl["make"](wl["sample_side"])
     t0 = time.perf_counter()
     po, bo = O.compress(system.n, system.rowptr, system.col, wl["tau"])
-    orc = O.Oracle(system.n, system.rowptr, system.col, system.val, po, bo, wl["levels"], wl["droptol"])
+    orc = O.Oracle(system.n, system.rowptr, system.col, system.val, po, bo, wl["levels"], wl["droptol"], 1, 0,
+                   wl["group_rows"])
     x, st, its, rel, _ = O.fgmres(system.n, system.rowptr, system.col, system.val, system.b, orc, TOL,
                                   wl["restart"], MAXIT)
     dt = time.perf_counter() - t0
@@ -94,6 +96,9 @@ def _comparators(wl, side, V, torch):
     single_perm = torch.arange(n, dtype=torch.int32, device="cuda")
     single_bptr = torch.arange(n + 1, dtype=torch.int32, device="cuda")
     methods = {"VBARMS": (wl["levels"], False), "VBILUT": (0, False), "ILUT (pointwise)": (0, True)}
+    if wl["group_rows"]:
+        methods = {"VBARMS (groups)": (wl["levels"], False), "VBARMS (one supernode per group)": (wl["levels"], False),
+                   "VBILUT": (0, False), "ILUT (pointwise)": (0, True)}
     out = {"comparators": {}, "workload": wl["desc"].replace("74^3", f"{side}^3").replace("40^3", f"{side}^3"),
            "n": n, "nnz": system.nnz, "tau": wl["tau"], "droptol": wl["droptol"], "krylov": f"FGMRES({wl['restart']})"}
     for name, (lev, pointwise) in methods.items():
@@ -105,7 +110,7 @@ def _comparators(wl, side, V, torch):
                 st = sv.set_partition(*dev, single_perm, single_bptr)
             else:
                 _, _, st = sv.compress(*dev, wl["tau"])
-            sv.factor(lev, wl["droptol"])
+            sv.factor(lev, wl["droptol"], group_rows=wl["group_rows"] if "(groups)" in name else 0)
             x, info = sv.solve(b, tol=TOL, restart=wl["restart"], maxit=MAXIT)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
@@ -236,6 +241,9 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
                     help="instead of the benchmark, time COUNT uneven systems with 16 right-hand sides each, "
                          "batched and one at a time")
+    ap.add_argument("--group-rows", type=int, default=-1, metavar="K",
+                    help="groups of supernodes in the independent sets, at most K rows each (0: one supernode; "
+                         "default: the workload's setting)")
     ap.add_argument("--comparators", type=int, default=0, metavar="SIDE",
                     help="instead of the benchmark, compare VBARMS with block ILUT alone (VBILUT, levels = 0) and "
                          "with pointwise ILUT (1x1 blocks, levels = 0) on a SIDE^3 grid of the workload's recipe")
@@ -266,6 +274,7 @@ def main() -> int:
         return _batch_bench(args, V, torch)
     wl = WORKLOADS[args.workload]
     tau, levels, droptol, restart = wl["tau"], wl["levels"], wl["droptol"], wl["restart"]
+    group_rows = wl["group_rows"] if args.group_rows < 0 else args.group_rows
     if args.comparators:
         return _comparators(wl, args.comparators, V, torch)
     system = wl["make"](wl["side"])
@@ -277,7 +286,7 @@ def main() -> int:
 
     def step(prec):
         _, _, st = sv.compress(rp, ci, va, tau)
-        sv.factor(levels, droptol, 1, V.F32 if prec == "f32" else V.F64)
+        sv.factor(levels, droptol, 1, V.F32 if prec == "f32" else V.F64, V.IS_NATURAL, group_rows)
         x, info = sv.solve(b, tol=TOL, restart=restart, maxit=MAXIT)
         return st, info
 
@@ -373,8 +382,8 @@ def main() -> int:
         "dtype": "f32 factors + f64 fgmres" if head == "f32" else "f64",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": system.n, "nnz": system.nnz, "blocks": R["st"].nblocks,
-                   "tau": tau, "levels": levels, "droptol": droptol, "krylov": f"FGMRES({restart})", "tol": TOL,
-                   "rhs": "A*1"},
+                   "tau": tau, "levels": levels, "droptol": droptol, "group_rows": group_rows,
+                   "krylov": f"FGMRES({restart})", "tol": TOL, "rhs": "A*1"},
         "runs": {p: summary(p) for p in precs},
         "device_memory_GiB": {"peak_live": round(mem["peak"] / 2**30, 2), "cached": round(mem["cached"] / 2**30, 2),
                               "runtime_allocs": mem["runtime_allocs"]},

@@ -131,7 +131,7 @@ __global__ void k_block_sq(int nis, const int *is_list, const int *rb, int64_t *
 template <class T>
 __global__ void k_gepp(int nis, const int *is_list, const int *rb, const int64_t *rp, const int *ci, const int *co,
                        const int64_t *wp, const int64_t *vp, const T *v, const int64_t *dlu_off, const int *is_rb,
-                       T *dlu, int *dpiv, double min_ratio, int lvl, int *err) {
+                       T *dlu, int *dpiv, int *dperm, double min_ratio, int lvl, int *err) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nis) return;
     int I = is_list[i];
@@ -143,15 +143,42 @@ __global__ void k_gepp(int nis, const int *is_list, const int *rb, const int64_t
     const T *a = v + vp[I] + co[k];
     for (int r = 0; r < m; ++r)
         for (int c = 0; c < m; ++c) d[r * m + c] = a[r * W + c];
-    if (!dev_gepp(m, d, dpiv + is_rb[i])) dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, I);
-    else dev_count_illcond<T>(m, d, min_ratio, err);
+    if (!dev_gepp(m, d, dpiv + is_rb[i])) {
+        dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, I);
+        return;
+    }
+    dev_count_illcond<T>(m, d, min_ratio, err);
+    // the row exchanges as one permutation: row r of P x is row dperm[r] of x
+    int *pm = dperm + is_rb[i];
+    const int *pv = dpiv + is_rb[i];
+    for (int r = 0; r < m; ++r) pm[r] = r;
+    for (int r = 0; r < m; ++r) {
+        const int t = pm[r];
+        pm[r] = pm[pv[r]];
+        pm[pv[r]] = t;
+    }
+}
+
+// x <- L^{-1} x (unit lower triangle of an LU) for a vector of up to MAXM entries held in
+// registers; the operations and their order are those of dev_lu_fwd after its exchanges.
+template <class T, int MAXM>
+__device__ inline void reg_l_fwd(int m, const T *lu, T (&x)[MAXM]) {
+#pragma unroll
+    for (int r = 0; r < MAXM; ++r) {
+        if (r < m) {
+            T s = x[r];
+#pragma unroll
+            for (int q = 0; q < r; ++q) s = s - lu[r * m + q] * x[q];
+            x[r] = s;
+        }
+    }
 }
 
 // G = L^{-1} P F: one lane per panel column of an independent block row (F columns only)
 template <class T>
-__global__ void k_compute_g(int p, int64_t nw, const int64_t *wp, const int64_t *vp, const int *rb, const int *sc,
+__global__ void __launch_bounds__(128) k_compute_g(int p, int64_t nw, const int64_t *wp, const int64_t *vp, const int *rb, const int *sc,
                             const int *colblk, const int *isf, const int *num, const T *v, const T *dlu,
-                            const int64_t *dlu_off, const int *dpiv, const int *is_rb, T *out) {
+                            const int64_t *dlu_off, const int *dperm, const int *is_rb, T *out) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nw) return;
     int I = (int)dev_floor(wp, 0, p + 1, g);
@@ -162,35 +189,58 @@ __global__ void k_compute_g(int p, int64_t nw, const int64_t *wp, const int64_t 
     int64_t W = wp[I + 1] - wp[I];
     int64_t c = g - wp[I];
     const T *a = v + vp[I] + c;
-    T x[VBARMS_MAX_BLOCK];
-    for (int r = 0; r < m; ++r) x[r] = a[r * W];
-    int i = num[I];
-    dev_lu_fwd<T, T>(m, dlu + dlu_off[i], dpiv + is_rb[i], x);
+    const int i = num[I];
+    const int *pm = dperm + is_rb[i];
+    T x[VBARMS_MAX_BLOCK];  // P applied while loading
+#pragma unroll
+    for (int r = 0; r < VBARMS_MAX_BLOCK; ++r) x[r] = r < m ? a[(int64_t)pm[r] * W] : T(0);
+    reg_l_fwd<T, VBARMS_MAX_BLOCK>(m, dlu + dlu_off[i], x);
     T *o = out + vp[I] + c;
-    for (int r = 0; r < m; ++r) o[r * W] = x[r];
+#pragma unroll
+    for (int r = 0; r < VBARMS_MAX_BLOCK; ++r)
+        if (r < m) o[r * W] = x[r];
 }
 
-// W = E U^{-1}: one lane per (block, row) of a remaining block row (E blocks only)
+// e <- e U^{-1} for a row of up to MAXM entries held in registers: the loops are unrolled
+// to MAXM with guards, so the row never leaves registers; the operations and their order
+// are those of dev_row_solve_u.
+template <class T, int MAXM>
+__device__ inline void reg_row_solve_u(int m, const T *lu, T (&e)[MAXM]) {
+#pragma unroll
+    for (int c = 0; c < MAXM; ++c) {
+        if (c < m) {
+            T s = e[c];
+#pragma unroll
+            for (int q = 0; q < c; ++q) s = s - e[q] * lu[q * m + c];
+            e[c] = s / lu[c * m + c];
+        }
+    }
+}
+
+// W = E U^{-1}: one lane per scalar row of a remaining block row, its E blocks in turn
 template <class T>
-__global__ void k_compute_w(int p, int64_t nb, int maxm, const int64_t *rp, const int *ci, const int *co,
+__global__ void __launch_bounds__(128) k_compute_w(int n, const int *rowblk, const int64_t *rp, const int *ci, const int *co,
                             const int64_t *wp, const int64_t *vp, const int *rb, const int *isf, const int *num,
                             const T *v, const T *dlu, const int64_t *dlu_off, T *out) {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t k = gid / maxm;
-    int r = (int)(gid % maxm);
-    if (k >= nb) return;
-    int I = (int)dev_floor(rp, 0, p + 1, k);
-    int m = rb[I + 1] - rb[I];
-    if (r >= m || isf[I]) return;
-    int J = ci[k];
-    if (!isf[J]) return;
-    int nJ = rb[J + 1] - rb[J];
-    int64_t W = wp[I + 1] - wp[I];
-    int64_t off = vp[I] + r * W + co[k];
-    T e[VBARMS_MAX_BLOCK];
-    for (int c = 0; c < nJ; ++c) e[c] = v[off + c];
-    dev_row_solve_u<T>(nJ, dlu + dlu_off[num[J]], e, 1);
-    for (int c = 0; c < nJ; ++c) out[off + c] = e[c];
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= n) return;
+    const int I = rowblk[row];
+    if (isf[I]) return;
+    const int r = row - rb[I];
+    const int64_t W = wp[I + 1] - wp[I];
+    for (int64_t k = rp[I]; k < rp[I + 1]; ++k) {
+        const int J = ci[k];
+        if (!isf[J]) continue;
+        const int nJ = rb[J + 1] - rb[J];
+        const int64_t off = vp[I] + r * W + co[k];
+        T e[VBARMS_MAX_BLOCK];
+#pragma unroll
+        for (int c = 0; c < VBARMS_MAX_BLOCK; ++c) e[c] = c < nJ ? v[off + c] : T(0);
+        reg_row_solve_u<T, VBARMS_MAX_BLOCK>(nJ, dlu + dlu_off[num[J]], e);
+#pragma unroll
+        for (int c = 0; c < VBARMS_MAX_BLOCK; ++c)
+            if (c < nJ) out[off + c] = e[c];
+    }
 }
 
 // keep flags of G (mode 0) or W (mode 1) blocks after the drop test
@@ -390,24 +440,56 @@ struct HostGroups {
     std::vector<int> gptr, members;  // members of group g: members[gptr[g] .. gptr[g+1])
 };
 
-HostGroups host_groups(int p, const std::vector<int64_t> &rp, const std::vector<int> &ci, const std::vector<int> &rb,
-                       int gmax, const std::vector<double> *wts) {
-    std::vector<int64_t> tp(p + 1, 0);
-    for (int c : ci) tp[c + 1]++;
-    for (int j = 0; j < p; ++j) tp[j + 1] += tp[j];
-    std::vector<int> tr(ci.size());
-    {
-        std::vector<int64_t> f(tp.begin(), tp.end() - 1);
-        for (int I = 0; I < p; ++I)
-            for (int64_t k = rp[I]; k < rp[I + 1]; ++k) tr[f[ci[k]]++] = I;
+// In-place ascending sort of a short list by one thread (Shell sort, gaps 701 .. 1); the
+// lists here hold tens to a few hundred entries.
+__device__ inline void dev_shell_sort(int *c, int64_t k) {
+    const int gaps[8] = {701, 301, 132, 57, 23, 10, 4, 1};
+    for (int gi = 0; gi < 8; ++gi) {
+        const int64_t gap = gaps[gi];
+        for (int64_t i = gap; i < k; ++i) {
+            const int v = c[i];
+            int64_t j = i;
+            while (j >= gap && c[j - gap] > v) {
+                c[j] = c[j - gap];
+                j -= gap;
+            }
+            c[j] = v;
+        }
     }
+}
+
+// Neighbour lists of the quotient graph of A + A^T, ascending and without the vertex
+// itself: the row list merged with the (sorted) column list.  Pass 0 counts, pass 1 writes.
+__global__ void k_sym_adj(int p, const int64_t *rp, const int *ci, const int64_t *tptr, int *tlist, int pass,
+                          int64_t *cnt, const int64_t *aptr, int *adj) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= p) return;
+    int *t = tlist + tptr[v];
+    const int64_t nt = tptr[v + 1] - tptr[v];
+    if (pass == 0) dev_shell_sort(t, nt);  // the column list was filled in arbitrary order
+    int64_t a = rp[v], ae = rp[v + 1], b = 0, c = 0;
+    int last = -1;
+    while (a < ae || b < nt) {
+        int x;
+        if (b >= nt || (a < ae && ci[a] <= t[b])) x = ci[a++];
+        else x = t[b++];
+        if (x == v || x == last) continue;
+        last = x;
+        if (pass == 1) adj[aptr[v] + c] = x;
+        ++c;
+    }
+    if (pass == 0) cnt[v] = c;
+}
+
+HostGroups host_groups(int p, const std::vector<int64_t> &ap, const std::vector<int> &adj, const std::vector<int> &rb,
+                       int gmax, const std::vector<double> *wts) {
     std::vector<int> order(p);
     for (int I = 0; I < p; ++I) order[I] = I;
     if (wts) std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return (*wts)[a] > (*wts)[b]; });
     HostGroups G;
     G.gid.assign(p, -1);
     std::vector<char> marked(p, 0);
-    std::vector<int> nbr, mem;
+    std::vector<int> mem;
     for (int v : order) {
         if (marked[v]) continue;
         const int g = G.ng++;
@@ -415,12 +497,8 @@ HostGroups host_groups(int p, const std::vector<int64_t> &rp, const std::vector<
         G.gid[v] = g;
         marked[v] = 1;
         mem.assign(1, v);
-        nbr.clear();
-        for (int64_t k = rp[v]; k < rp[v + 1]; ++k) nbr.push_back(ci[k]);
-        for (int64_t k = tp[v]; k < tp[v + 1]; ++k) nbr.push_back(tr[k]);
-        std::sort(nbr.begin(), nbr.end());
-        for (size_t a = 0; a < nbr.size(); ++a) {
-            const int u = nbr[a];
+        for (int64_t a = ap[v]; a < ap[v + 1]; ++a) {  // neighbours ascending
+            const int u = adj[a];
             if (marked[u]) continue;
             const int su = rb[u + 1] - rb[u];
             if (rows + su > gmax) continue;
@@ -429,10 +507,8 @@ HostGroups host_groups(int p, const std::vector<int64_t> &rp, const std::vector<
             mem.push_back(u);
             rows += su;
         }
-        for (int w : mem) {
-            for (int64_t k = rp[w]; k < rp[w + 1]; ++k) marked[ci[k]] = 1;
-            for (int64_t k = tp[w]; k < tp[w + 1]; ++k) marked[tr[k]] = 1;
-        }
+        for (int w : mem)
+            for (int64_t a = ap[w]; a < ap[w + 1]; ++a) marked[adj[a]] = 1;
     }
     std::vector<int> renum(G.ng, -1);
     int seen = 0;
@@ -472,15 +548,7 @@ __global__ void k_rg_cand(int pc, const int *mptr, const int *mem, const int64_t
         const int I = mem[a];
         for (int64_t k = rp[I]; k < rp[I + 1]; ++k) c[k2++] = cblk[ci[k]];
     }
-    for (int64_t i = 1; i < k2; ++i) {  // insertion sort: the members' lists are sorted runs
-        const int v = c[i];
-        int64_t j = i - 1;
-        while (j >= 0 && c[j] > v) {
-            c[j + 1] = c[j];
-            --j;
-        }
-        c[j + 1] = v;
-    }
+    dev_shell_sort(c, k2);  // several hundred entries for a group of many members
     int64_t u = 0;
     for (int64_t i = 0; i < k2; ++i)
         if (u == 0 || c[i] != c[u - 1]) c[u++] = c[i];
@@ -498,30 +566,41 @@ __global__ void k_rg_crow(int p, const int *rb, const int *cblk, const int *coff
     const int base = crb[cblk[I]] + coff[I];
     for (int r = 0; r < rb[I + 1] - rb[I]; ++r) crow[base + r] = rb[I] + r;
 }
-// Scatter of the level matrix into the coarse panel (zeroed beforehand), one thread per
-// level row: every block (I, J) lands in coarse block (cblk[I], cblk[J]) at row offset
-// coff[I] and column offset coff[J].
+// Coarse panel column of every panel column of the level matrix: block (I, J) lands in
+// coarse block (cblk[I], cblk[J]) at column offset coff[J].  One thread per block row.
+__global__ void k_rg_cols_map(int p, const int *rb, const int64_t *rp, const int *ci, const int *co, const int64_t *wp,
+                              const int *cblk, const int *coff, const int64_t *crp, const int *cci, const int *cco,
+                              int *dstpc, int *err) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= p) return;
+    const int X = cblk[I];
+    for (int64_t k = rp[I]; k < rp[I + 1]; ++k) {
+        const int J = ci[k];
+        const int64_t pos = dev_find(cci, crp[X], crp[X + 1], cblk[J]);
+        if (pos < 0) { dev_set_error(err, VBARMS_ERR_HIP, 2010, I); return; }
+        const int dc = cco[pos] + coff[J];
+        for (int c = 0; c < rb[J + 1] - rb[J]; ++c) dstpc[wp[I] + co[k] + c] = dc + c;
+    }
+}
+// Scatter of the level matrix into the coarse panel (zeroed beforehand): 16 lanes per level
+// row stream its panel row; row r of block I is row coff[I] + r of coarse block cblk[I].
 template <class T>
-__global__ void k_rg_vals(int n, const int *rowblk, const int *rb, const int64_t *rp, const int *ci, const int *co,
-                          const int64_t *wp, const int64_t *vp, const T *v, const int *cblk, const int *coff,
-                          const int64_t *crp, const int *cci, const int *cco, const int64_t *cwp, const int64_t *cvp,
-                          T *cv, int *err) {
-    int fr = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_rg_vals(int n, const int *rowblk, const int *rb, const int64_t *wp, const int64_t *vp, const T *v,
+                          const int *cblk, const int *coff, const int *dstpc, const int64_t *cwp, const int64_t *cvp,
+                          T *cv) {
+    constexpr int G = 16;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t fr = gid / G;
+    const int lane = (int)(gid % G);
     if (fr >= n) return;
     const int I = rowblk[fr];
-    const int r = fr - rb[I];
+    const int r = (int)(fr - rb[I]);
     const int X = cblk[I];
     const int64_t W = wp[I + 1] - wp[I], CW = cwp[X + 1] - cwp[X];
     const T *src = v + vp[I] + r * W;
     T *dst = cv + cvp[X] + (int64_t)(coff[I] + r) * CW;
-    for (int64_t k = rp[I]; k < rp[I + 1]; ++k) {
-        const int J = ci[k];
-        const int nJ = rb[J + 1] - rb[J];
-        const int64_t pos = dev_find(cci, crp[X], crp[X + 1], cblk[J]);
-        if (pos < 0) { dev_set_error(err, VBARMS_ERR_HIP, 2010, I); return; }
-        const int64_t dc = cco[pos] + coff[J];
-        for (int c = 0; c < nJ; ++c) dst[dc + c] = src[co[k] + c];
-    }
+    const int *pc = dstpc + wp[I];
+    for (int64_t c = lane; c < W; c += G) dst[pc[c]] = src[c];
 }
 // level row of every row of a block list, in the list's own numbering (IS or rest)
 __global__ void k_row_maps(int nb, const int *list, const int *rb, const int *off, const int *crow, int *out) {
@@ -599,10 +678,14 @@ void regroup_panel(const Panel<T> &A, const HostGroups &G, Panel<T> &Ac, DBuf<in
         k_rg_crow<<<grid_for(p, 256), 256, 0, s>>>(p, A.rb.p, d_cblk.p, d_coff.p, Ac.rb.p, crow.p);
         VB_LAUNCH_CHECK();
     }
-    if (n > 0) {
-        k_rg_vals<T><<<grid_for(n, 128), 128, 0, s>>>(n, A.rowblk.p, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, A.vp.p,
-                                                       A.v.p, d_cblk.p, d_coff.p, Ac.rp.p, Ac.ci.p, Ac.co.p, Ac.wp.p,
-                                                       Ac.vp.p, Ac.v.p, err);
+    if (p > 0) {
+        DBuf<int> dstpc(std::max<int64_t>(A.nw, 1));
+        k_rg_cols_map<<<grid_for(p, 128), 128, 0, s>>>(p, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, d_cblk.p, d_coff.p,
+                                                        Ac.rp.p, Ac.ci.p, Ac.co.p, dstpc.p, err);
+        VB_LAUNCH_CHECK();
+        k_rg_vals<T><<<grid_for((int64_t)n * 16, 256), 256, 0, s>>>(n, A.rowblk.p, A.rb.p, A.wp.p, A.vp.p, A.v.p,
+                                                                     d_cblk.p, d_coff.p, dstpc.p, Ac.wp.p, Ac.vp.p,
+                                                                     Ac.v.p);
         VB_LAUNCH_CHECK();
     }
 }
@@ -655,13 +738,41 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
             VB_LAUNCH_CHECK();
         }
         if (grouped) {
-            std::vector<int64_t> hrp;
-            std::vector<int> hci;
+            // the quotient graph's neighbour lists are built on the device; the host receives
+            // p + 1 offsets and about nb neighbours
+            std::vector<int64_t> hap;
+            std::vector<int> hadj;
             std::vector<double> hw;
-            to_host(hrp, As.rp.p, p + 1, s);
-            to_host(hci, As.ci.p, As.nb, s);
+            {
+                DBuf<int> tcnt(std::max(p, 1)), tfill(std::max(p, 1));
+                DBuf<int64_t> tptr(p + 1), acnt(std::max(p, 1)), aptr(p + 1);
+                fill_i32(tcnt.p, 0, p, s);
+                fill_i32(tfill.p, 0, p, s);
+                if (p > 0) {
+                    k_tcount<<<grid_for(p, 256), 256, 0, s>>>(p, As.rp.p, As.ci.p, tcnt.p);
+                    VB_LAUNCH_CHECK();
+                }
+                const int64_t nt = scan_i32_to_i64(tcnt.p, tptr.p, p, s);
+                DBuf<int> tlist(std::max<int64_t>(nt, 1));
+                if (p > 0) {
+                    k_tfill<<<grid_for(p, 256), 256, 0, s>>>(p, As.rp.p, As.ci.p, tptr.p, tfill.p, tlist.p);
+                    VB_LAUNCH_CHECK();
+                    k_sym_adj<<<grid_for(p, 128), 128, 0, s>>>(p, As.rp.p, As.ci.p, tptr.p, tlist.p, 0, acnt.p,
+                                                                nullptr, nullptr);
+                    VB_LAUNCH_CHECK();
+                }
+                const int64_t na = scan_i64(acnt.p, aptr.p, p, s);
+                DBuf<int> adj(std::max<int64_t>(na, 1));
+                if (p > 0) {
+                    k_sym_adj<<<grid_for(p, 128), 128, 0, s>>>(p, As.rp.p, As.ci.p, tptr.p, tlist.p, 1, nullptr,
+                                                                aptr.p, adj.p);
+                    VB_LAUNCH_CHECK();
+                }
+                to_host(hap, aptr.p, p + 1, s);
+                to_host(hadj, adj.p, na, s);
+            }
             if (is_order == 1) to_host(hw, wts.p, p, s);
-            G = host_groups(p, hrp, hci, As.h_rb, group_rows, is_order == 1 ? &hw : nullptr);
+            G = host_groups(p, hap, hadj, As.h_rb, group_rows, is_order == 1 ? &hw : nullptr);
             regroup_panel(As, G, Ac, crow, err, s);
             state.alloc(std::max(Ac.p, 1));
             fill_i32(state.p, 1, G.ng, s);
@@ -739,6 +850,7 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
     const int nis = L.nis, nrest = L.nrest;
 
     // Step 4: pivot blocks
+    DBuf<int> dperm(std::max(L.n_is, 1));  // row exchanges of every pivot block as a permutation
     L.dlu_off.alloc(nis + 1);
     {
         DBuf<int64_t> sq(std::max(nis, 1));
@@ -751,7 +863,7 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
         L.dpiv.alloc(std::max(L.n_is, 1));
         if (nis > 0) {
             k_gepp<T><<<grid_for(nis, 64), 64, 0, s>>>(nis, L.is_list.p, As.rb.p, As.rp.p, As.ci.p, As.co.p, As.wp.p,
-                                                      As.vp.p, As.v.p, L.dlu_off.p, L.is_rb.p, L.dlu.p, L.dpiv.p,
+                                                      As.vp.p, As.v.p, L.dlu_off.p, L.is_rb.p, L.dlu.p, L.dpiv.p, dperm.p,
                                                       min_ratio, lvl,
                                                       err);
             VB_LAUNCH_CHECK();
@@ -777,9 +889,9 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
     if (As.nw > 0) {
         k_compute_g<T><<<grid_for(As.nw, 128), 128, 0, s>>>(pw, As.nw, As.wp.p, As.vp.p, As.rb.p, As.sc.p,
                                                              As.rowblk.p, L.is_flag.p, L.num.p, As.v.p, L.dlu.p,
-                                                             L.dlu_off.p, L.dpiv.p, L.is_rb.p, tmp.p);
+                                                             L.dlu_off.p, dperm.p, L.is_rb.p, tmp.p);
         VB_LAUNCH_CHECK();
-        k_compute_w<T><<<grid_for(As.nb * As.maxm, 128), 128, 0, s>>>(pw, As.nb, As.maxm, As.rp.p, As.ci.p, As.co.p,
+        k_compute_w<T><<<grid_for(n, 128), 128, 0, s>>>(n, As.rowblk.p, As.rp.p, As.ci.p, As.co.p,
                                                                        As.wp.p, As.vp.p, As.rb.p, L.is_flag.p,
                                                                        L.num.p, As.v.p, L.dlu.p, L.dlu_off.p, tmp.p);
         VB_LAUNCH_CHECK();

@@ -50,6 +50,36 @@ WORKLOADS = {
 }
 
 
+def _sources_sha256():
+    """Hash of the library's kernel and header sources (a traffic record applies only to the
+    sources it was measured on)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1508_02219_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h")))
+    for f in files + [os.path.join(ROOT, "include", "vbarms.h")]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _traffic(kernel, workload, group_rows):
+    """HBM bytes per dispatch of `kernel` from the committed counter record (FETCH_SIZE and
+    WRITE_SIZE scaled by the copy calibration), or None when no record matches this kernel,
+    this workload and the current sources."""
+    path = os.path.join(ROOT, "profiles", "k_ilut_wave_upwind74_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if (rec.get("kernel") != kernel or workload != "upwind74" or group_rows != 32
+            or rec.get("sources_sha256") != _sources_sha256()):
+        return None
+    return rec["bytes_per_dispatch"]
+
+
 def _host_cpu():
     model = platform.processor() or ""
     try:
@@ -371,6 +401,9 @@ def main() -> int:
                 "bytes_per_launch": round(nbytes / calls), "achieved": None if achieved is None else round(achieved, 3),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": None if achieved is None else round(achieved / HBM_PEAK_GBPS, 6), "traffic": None}
+    if dom == "ilut_wave":
+        roofline["traffic"] = _traffic("k_ilut_wave<float>" if head == "f32" else "k_ilut_wave<double>",
+                                       args.workload, group_rows)
 
     def summary(prec):
         r = runs[prec]

@@ -842,3 +842,56 @@ def test_pivoting_zero_drop_identity_and_ilut(orc, mode):
     # the multipliers are L_ik = w_k D_k^{-1}: check one against a dense solve
     Lb = o.matrix(orc.L)
     assert Lb.nb > 0
+
+
+# --------------------------------------------------------------------------------------
+# Inputs on which the first GPU version faulted (kept off the GPU): valid on the CPU
+# --------------------------------------------------------------------------------------
+def _panel_layout_in_bounds(bm):
+    """Restates the panel layout of a block matrix (row widths, value offsets, block column
+    offsets, scalar columns) and checks every index it produces against its array."""
+    rs, cs = np.diff(bm.rb), np.diff(bm.cb)
+    assert rs.max(initial=0) <= 32 and cs.max(initial=0) <= 32
+    nv = 0
+    n_cols = int(bm.cb[-1])
+    for i in range(bm.p):
+        ks = range(bm.rowptr[i], bm.rowptr[i + 1])
+        cols = [int(bm.colidx[k]) for k in ks]
+        assert cols == sorted(set(cols)) and all(0 <= c < bm.q for c in cols)
+        width = int(sum(cs[c] for c in cols))
+        co = np.concatenate([[0], np.cumsum([cs[c] for c in cols])])[:-1] if cols else np.zeros(0, int)
+        for c, o in zip(cols, co):
+            assert o + cs[c] <= width
+            sc = np.arange(bm.cb[c], bm.cb[c + 1])
+            assert sc.min() >= 0 and sc.max() < n_cols
+        nv += int(rs[i]) * width
+    assert nv == int(bm.voff[-1])
+
+
+@pytest.mark.parametrize("case", ["smoke_8x8x6", "tiny_2x2x1_seed0", "tiny_2x2x1_seed1", "tiny_2x2x1_seed2"])
+def test_inputs_that_faulted_the_first_gpu_version_are_valid_on_the_cpu(orc, case):
+    """The smoke input (8x8x6 14-neighbour grid, ell = 5, tau = 0.8, 3 levels, t = 1e-4) and a
+    2x2x1 7-point grid (ell = 2, tau = 1, levels = 0, t = 0) ended the first GPU version with
+    a memory fault; they stay off the GPU.  On the CPU every intermediate is well formed:
+    the partition is a permutation into blocks of at most 32 rows, every level matrix and
+    factor has a panel layout whose indices stay inside its arrays, and the factorization is
+    what the method prescribes (the exact inverse at t = 0)."""
+    if case == "smoke_8x8x6":
+        s = synth.grid_system(8, 8, 6, ell=5, stencil="14rand", perturb=0.10, seed=2)
+        tau, levels, t = 0.8, 3, 1e-4
+    else:
+        s = synth.grid_system(2, 2, 1, ell=2, stencil="7pt", seed=int(case[-1]))
+        tau, levels, t = 1.0, 0, 0.0
+    o, perm, bptr = _oracle(orc, s, tau, levels, t)
+    assert o.status == 0
+    assert sorted(perm.tolist()) == list(range(s.n))
+    assert bptr[0] == 0 and bptr[-1] == s.n and np.all(np.diff(bptr) >= 1) and np.diff(bptr).max() <= 32
+    for lvl in range(o.nlevels):
+        for w in (orc.A, orc.AS, orc.G, orc.W):
+            _panel_layout_in_bounds(o.matrix(w, lvl))
+    for w in (orc.LAST, orc.L, orc.U):
+        _panel_layout_in_bounds(o.matrix(w))
+    if t == 0.0:
+        x = np.random.default_rng(0).standard_normal(s.n)
+        ye = np.linalg.solve(s.dense(), x)
+        assert np.abs(o.apply(x) - ye).max() <= 1e-10 * np.abs(ye).max()

@@ -196,6 +196,7 @@ def _batch_bench(args, V, torch):
     import numpy as np
 
     count, nrhs, tau, levels, droptol, restart = args.batch, 16, 0.8, 3, 1e-4, 50
+    group_rows = max(args.group_rows, 0)
     t0 = time.perf_counter()
     systems = _batch_systems(count)
     print(f"[bench] generated {count} systems (n = {sum(s.n for s in systems)}) in "
@@ -215,7 +216,7 @@ def _batch_bench(args, V, torch):
     def batched():
         info = []
         for (a, b), Bq in zip(chunks, Bc):
-            bs.factor(devs[a:b], tau, levels, droptol)
+            bs.factor(devs[a:b], tau, levels, droptol, group_rows=group_rows)
             X, inf = bs.solve(Bq, tol=TOL, restart=restart, maxit=MAXIT)
             info += [list(r) for r in zip(*inf)]  # per system: its right-hand sides
         return info
@@ -238,13 +239,13 @@ def _batch_bench(args, V, torch):
     sv = V.Solver()
     for q in sample[:1]:  # warm-up
         sv.compress(*devs[q], tau)
-        sv.factor(levels, droptol)
+        sv.factor(levels, droptol, group_rows=group_rows)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     n_sample = 0
     for q in sample:
         sv.compress(*devs[q], tau)
-        sv.factor(levels, droptol)
+        sv.factor(levels, droptol, group_rows=group_rows)
         for r in range(nrhs):
             x, inf = sv.solve(B[r, off[q]:off[q + 1]].contiguous(), tol=TOL, restart=restart, maxit=MAXIT)
             ok = ok and inf.status == 0
@@ -261,7 +262,10 @@ def _batch_bench(args, V, torch):
                                   f"{{3, 5, 6}}, {nrhs} N(0,1) right-hand sides each", "systems": count,
                       "n_total": N, "nnz_total": int(sum(s.nnz for s in systems)), "tau": tau, "levels": levels,
                       "droptol": droptol, "krylov": f"FGMRES({restart})", "tol": TOL,
-                      "systems_per_batched_factorization": chunk, "batched_factorizations": len(chunks)},
+                      "systems_per_batched_factorization": chunk, "batched_factorizations": len(chunks),
+                      "group_rows": group_rows,
+                      "right_hand_sides": "all 16 of a chunk in one lockstep FGMRES (multi-vector SpMV and "
+                                          "preconditioner launches)"},
            "all_converged": bool(ok), "iters_min_median_max": [int(min(its)), int(np.median(its)), int(max(its))],
            "batched_s": round(tb, 4), "last_chunk_phases_ms": {"compress": round(fs.compress_ms, 2),
                                                             "factor": round(fs.factor_ms, 2),

@@ -248,13 +248,14 @@ void refactor_fp64(vbarms_t h) {
 }
 
 // M^{-1} in the compressed numbering
-void precond_apply(vbarms_t h, const double *x, double *y) {
+// y = M^{-1} x for nv vectors (n apart), in the compressed numbering
+void precond_apply(vbarms_t h, const double *x, double *y, int nv = 1) {
     if (h->precision == VBARMS_F32) {
-        KScope ks(VBARMS_K_APPLY, h->f32->apply_bytes, h->stream);
-        solve_levels<float>(*h->f32, 0, x, y, h->err.rec.p, h->stream);
+        KScope ks(VBARMS_K_APPLY, h->f32->apply_bytes * nv, h->stream);
+        solve_levels<float>(*h->f32, 0, x, y, nv, h->err.rec.p, h->stream);
     } else {
-        KScope ks(VBARMS_K_APPLY, h->f64->apply_bytes, h->stream);
-        solve_levels<double>(*h->f64, 0, x, y, h->err.rec.p, h->stream);
+        KScope ks(VBARMS_K_APPLY, h->f64->apply_bytes * nv, h->stream);
+        solve_levels<double>(*h->f64, 0, x, y, nv, h->err.rec.p, h->stream);
     }
 }
 
@@ -344,7 +345,9 @@ void need_factors(vbarms_t h) {
 struct vbarms_batch_ctx {
     vbarms_t h = nullptr;          // handle of the combined system
     std::vector<int64_t> off;      // first row of every system in the combined numbering
-    Segments seg;
+    Segments seg;                  // the systems of one vector
+    Segments segv;                 // the systems of seg_nv vectors one after another
+    int seg_nv = 0;
     BatchKrylovWork kw;
     std::string last_error;
     bool have_factors = false;
@@ -668,6 +671,8 @@ int vbarms_batch_destroy(vbarms_batch_t b) {
         StreamScope scope(h->stream);  // buffers are released in stream order
         (void)hipSetDevice(h->device);
         b->seg = Segments();
+        b->segv = Segments();
+        b->seg_nv = 0;
         b->kw = BatchKrylovWork();
     }
     delete b;
@@ -719,6 +724,7 @@ int vbarms_batch_factor(vbarms_batch_t b, int32_t nsys, const vbarms_csr *system
         // compressed numbering.
         b->off = off;
         b->seg.build(off, s);
+        b->seg_nv = 0;  // the multi-vector segments follow the new systems
         rc = vbarms_factor(h, p);
         if (rc != VBARMS_OK) fail(rc, std::string("batch factor: ") + h->last_error);
         b->have_factors = true;
@@ -743,20 +749,40 @@ int vbarms_batch_solve(vbarms_batch_t b, const double *B, double *X, int32_t nrh
         Timer tm(s);
         const int64_t n = b->off.back();
         const int ns = b->seg.nseg;
-        DBuf<double> bc(std::max<int64_t>(n, 1)), xc(std::max<int64_t>(n, 1));
-        auto pre = [&](const double *in, double *out) { precond_apply(h, in, out); };
+        // right-hand sides per lockstep run: the Krylov bases of a vector take
+        // (2 restart + 1) n doubles; a run keeps them within a third of the device
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = (size_t)64 << 30;
+        const double per_rhs = 8.0 * (2.0 * restart + 4.0) * (double)std::max<int64_t>(n, 1);
+        const int wave = (int)std::max<double>(
+            1.0, std::min<double>(std::min(nrhs, 1024), std::floor(tot / 3.0 / per_rhs)));
+        DBuf<double> bc((size_t)std::max<int64_t>(n, 1) * wave), xc((size_t)std::max<int64_t>(n, 1) * wave);
+        auto pre = [&](const double *in, double *out, int nv) { precond_apply(h, in, out, nv); };
         std::vector<vbarms_sinfo> inf;
         int worst = VBARMS_OK;
-        for (int r = 0; r < nrhs; ++r) {
+        for (int r0 = 0; r0 < nrhs; r0 += wave) {
+            const int nv = std::min(wave, nrhs - r0);
+            if (b->seg_nv != nv) {  // segments of nv copies of the combined numbering
+                std::vector<int64_t> offv((size_t)nv * ns + 1);
+                for (int r = 0; r < nv; ++r)
+                    for (int q = 0; q < ns; ++q) offv[(size_t)r * ns + q] = (int64_t)r * n + b->off[q];
+                offv[(size_t)nv * ns] = (int64_t)nv * n;
+                b->segv.build(offv, s);
+                b->seg_nv = nv;
+            }
             h->err.reset(s);
-            gather_perm((int)n, h->perm.p, B + (int64_t)r * n, bc.p, s);
-            gather_perm((int)n, h->perm.p, X + (int64_t)r * n, xc.p, s);
-            const int st = fgmres_batch_run(h->A, b->kw, b->seg, bc.p, xc.p, tol, restart, maxit, pre, inf, s);
+            for (int r = 0; r < nv; ++r) {
+                gather_perm((int)n, h->perm.p, B + (int64_t)(r0 + r) * n, bc.p + (int64_t)r * n, s);
+                gather_perm((int)n, h->perm.p, X + (int64_t)(r0 + r) * n, xc.p + (int64_t)r * n, s);
+            }
+            const int st = fgmres_batch_run(h->A, nv, b->kw, b->segv, bc.p, xc.p, tol, restart, maxit, pre, inf, s);
             check_dev_err(h, "batch solve");
-            scatter_perm((int)n, h->perm.p, xc.p, X + (int64_t)r * n, s);
+            for (int r = 0; r < nv; ++r)
+                scatter_perm((int)n, h->perm.p, xc.p + (int64_t)r * n, X + (int64_t)(r0 + r) * n, s);
             if (st != VBARMS_OK) worst = VBARMS_NOT_CONVERGED;
             if (info)
-                for (int q = 0; q < ns; ++q) info[(int64_t)r * ns + q] = inf[q];
+                for (int r = 0; r < nv; ++r)
+                    for (int q = 0; q < ns; ++q) info[(int64_t)(r0 + r) * ns + q] = inf[(size_t)r * ns + q];
         }
         VB_HIP(hipStreamSynchronize(s));
         h->stats.solve_ms = tm.stop();

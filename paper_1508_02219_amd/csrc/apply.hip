@@ -7,6 +7,8 @@
 //   z = next level (or the last-level block ILUT solve) on g'
 //   u_i = U_i^{-1} (y - G z)_i                         row-streamed SpMV with G, then per block
 //   x_l = S2 P_I^T (u, z)
+// Several vectors go through at once: every kernel takes the vector from blockIdx.y, each
+// array holding its vectors one after another (ld apart).
 #include "factor.h"
 
 namespace vb {
@@ -17,9 +19,12 @@ constexpr int kTG = 8;
 
 template <class T>
 __global__ void k_lvl_down(int nis, const int *is_rows, const int *is_rb, const double *s1, const double *b,
-                           const T *dlu, const int64_t *dlu_off, const int *dpiv, double *y) {
+                           int64_t ldb, const T *dlu, const int64_t *dlu_off, const int *dpiv, double *y,
+                           int64_t ldy) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nis) return;
+    b += blockIdx.y * ldb;
+    y += blockIdx.y * ldy;
     const int m = is_rb[i + 1] - is_rb[i];
     const int *rows = is_rows + is_rb[i];
     double x[VBARMS_MAX_BLOCK];
@@ -33,9 +38,12 @@ __global__ void k_lvl_down(int nis, const int *is_rows, const int *is_rb, const 
 template <class T>
 __global__ void __launch_bounds__(256) k_lvl_spmv(int64_t nrows, const int *rowblk, const int *prb, const int64_t *wp,
                                                   const int64_t *vp, const int *sc, const T *pv, const double *v,
-                                                  const int *rows, const double *s1, const double *base,
-                                                  double *out) {
+                                                  int64_t ldv, const int *rows, const double *s1, const double *base,
+                                                  int64_t ldbase, double *out, int64_t ldout) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    v += blockIdx.y * ldv;
+    base += blockIdx.y * ldbase;
+    out += blockIdx.y * ldout;
     int64_t rr = gid / kTG;
     int lane = (int)(gid % kTG);
     double acc = 0.0;
@@ -63,9 +71,11 @@ __global__ void __launch_bounds__(256) k_lvl_spmv(int64_t nrows, const int *rowb
 
 template <class T>
 __global__ void k_lvl_up(int nis, const int *is_rows, const int *is_rb, const double *s2, const T *dlu,
-                         const int64_t *dlu_off, const double *t, double *x) {
+                         const int64_t *dlu_off, const double *t, int64_t ldt, double *x, int64_t ldx) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nis) return;
+    t += blockIdx.y * ldt;
+    x += blockIdx.y * ldx;
     const int m = is_rb[i + 1] - is_rb[i];
     const int *rows = is_rows + is_rb[i];
     double u[VBARMS_MAX_BLOCK];
@@ -74,9 +84,12 @@ __global__ void k_lvl_up(int nis, const int *is_rows, const int *is_rb, const do
     for (int r = 0; r < m; ++r) x[rows[r]] = s2[rows[r]] * u[r];
 }
 
-__global__ void k_lvl_rest_out(int64_t nrest_rows, const int *rest_rows, const double *s2, const double *z, double *x) {
+__global__ void k_lvl_rest_out(int64_t nrest_rows, const int *rest_rows, const double *s2, const double *z,
+                               int64_t ldz, double *x, int64_t ldx) {
     int64_t rr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (rr >= nrest_rows) return;
+    z += blockIdx.y * ldz;
+    x += blockIdx.y * ldx;
     const int row = rest_rows[rr];
     x[row] = s2[row] * z[rr];
 }
@@ -84,44 +97,50 @@ __global__ void k_lvl_rest_out(int64_t nrest_rows, const int *rest_rows, const d
 }  // namespace
 
 template <class T>
-void solve_levels(Factors<T> &f, int lvl, const double *b, double *x, int *err, hipStream_t s) {
+void solve_levels(Factors<T> &f, int lvl, const double *b, double *x, int nv, int *err, hipStream_t s) {
     if (lvl == f.nlev) {
-        solve_last(f.last, b, x, err, s);
+        solve_last(f.last, b, x, err, s, nv);
         return;
     }
     Level<T> &L = f.lev[lvl];
-    if (!L.g.p) {
-        L.g.alloc(std::max(L.n_rest, 1));
-        L.z.alloc(std::max(L.n_rest, 1));
+    if (L.ws_nv < nv) {  // workspaces for nv vectors
+        L.y.alloc((size_t)std::max(L.n_is, 1) * nv);
+        L.t.alloc((size_t)std::max(L.n_is, 1) * nv);
+        L.g.alloc((size_t)std::max(L.n_rest, 1) * nv);
+        L.z.alloc((size_t)std::max(L.n_rest, 1) * nv);
+        L.ws_nv = nv;
     }
+    const int64_t n = L.n, nis = L.n_is, nr = L.n_rest;
+    const unsigned vy = (unsigned)nv;
     if (L.nis > 0) {
-        k_lvl_down<T><<<grid_for(L.nis, 64), 64, 0, s>>>(L.nis, L.is_rows.p, L.is_rb.p, L.s1.p, b, L.dlu.p,
-                                                          L.dlu_off.p, L.dpiv.p, L.y.p);
+        k_lvl_down<T><<<dim3(grid_for(L.nis, 64), vy), 64, 0, s>>>(L.nis, L.is_rows.p, L.is_rb.p, L.s1.p, b, n,
+                                                                    L.dlu.p, L.dlu_off.p, L.dpiv.p, L.y.p, nis);
         VB_LAUNCH_CHECK();
     }
     if (L.n_rest > 0) {
-        k_lvl_spmv<T><<<grid_for((int64_t)L.n_rest * kTG, 256), 256, 0, s>>>(
-            L.n_rest, L.W.rowblk.p, L.W.rb.p, L.W.wp.p, L.W.vp.p, L.W.sc.p, L.W.v.p, L.y.p, L.rest_rows.p, L.s1.p, b,
-            L.g.p);
+        k_lvl_spmv<T><<<dim3(grid_for((int64_t)L.n_rest * kTG, 256), vy), 256, 0, s>>>(
+            L.n_rest, L.W.rowblk.p, L.W.rb.p, L.W.wp.p, L.W.vp.p, L.W.sc.p, L.W.v.p, L.y.p, nis, L.rest_rows.p, L.s1.p,
+            b, n, L.g.p, nr);
         VB_LAUNCH_CHECK();
     }
-    solve_levels(f, lvl + 1, L.g.p, L.z.p, err, s);
+    solve_levels(f, lvl + 1, L.g.p, L.z.p, nv, err, s);
     if (L.nis > 0) {
-        k_lvl_spmv<T><<<grid_for((int64_t)L.n_is * kTG, 256), 256, 0, s>>>(L.n_is, L.G.rowblk.p, L.G.rb.p, L.G.wp.p,
-                                                                             L.G.vp.p, L.G.sc.p, L.G.v.p, L.z.p,
-                                                                             nullptr, nullptr, L.y.p, L.t.p);
+        k_lvl_spmv<T><<<dim3(grid_for((int64_t)L.n_is * kTG, 256), vy), 256, 0, s>>>(
+            L.n_is, L.G.rowblk.p, L.G.rb.p, L.G.wp.p, L.G.vp.p, L.G.sc.p, L.G.v.p, L.z.p, nr, nullptr, nullptr, L.y.p,
+            nis, L.t.p, nis);
         VB_LAUNCH_CHECK();
-        k_lvl_up<T><<<grid_for(L.nis, 64), 64, 0, s>>>(L.nis, L.is_rows.p, L.is_rb.p, L.s2.p, L.dlu.p, L.dlu_off.p,
-                                                        L.t.p, x);
+        k_lvl_up<T><<<dim3(grid_for(L.nis, 64), vy), 64, 0, s>>>(L.nis, L.is_rows.p, L.is_rb.p, L.s2.p, L.dlu.p,
+                                                                  L.dlu_off.p, L.t.p, nis, x, n);
         VB_LAUNCH_CHECK();
     }
     if (L.n_rest > 0) {
-        k_lvl_rest_out<<<grid_for(L.n_rest, 256), 256, 0, s>>>(L.n_rest, L.rest_rows.p, L.s2.p, L.z.p, x);
+        k_lvl_rest_out<<<dim3(grid_for(L.n_rest, 256), vy), 256, 0, s>>>(L.n_rest, L.rest_rows.p, L.s2.p, L.z.p, nr,
+                                                                          x, n);
         VB_LAUNCH_CHECK();
     }
 }
 
-template void solve_levels<double>(Factors<double> &, int, const double *, double *, int *, hipStream_t);
-template void solve_levels<float>(Factors<float> &, int, const double *, double *, int *, hipStream_t);
+template void solve_levels<double>(Factors<double> &, int, const double *, double *, int, int *, hipStream_t);
+template void solve_levels<float>(Factors<float> &, int, const double *, double *, int, int *, hipStream_t);
 
 }  // namespace vb

@@ -1,7 +1,8 @@
 // Batched solves of independent systems (several systems factored as one block-diagonal
-// matrix) with right-preconditioned FGMRES(m) run for all of them in lockstep: every
-// kernel of a step covers every system, while the inner products, the Hessenberg matrices,
-// the Givens rotations, convergence and restarts are kept per system.
+// matrix) with right-preconditioned FGMRES(m) run for all of them, and for several
+// right-hand sides, in lockstep: every kernel of a step covers every system and vector,
+// while the inner products, the Hessenberg matrices, the Givens rotations, convergence and
+// restarts are kept per system and vector.
 //
 // Systems occupy consecutive row ranges ("segments") of the combined numbering.  The dot
 // products are reduced per segment in a fixed order (chunk partials, then the chunks of a
@@ -151,10 +152,11 @@ void BatchKrylovWork::ensure(int64_t n_, int m_, int nseg_, int nchunk_) {
     }
 }
 
-int fgmres_batch_run(const Panel<double> &A, BatchKrylovWork &kw, const Segments &sg, const double *b, double *x,
-                     double tol, int m, int maxit, const std::function<void(const double *, double *)> &precond,
+int fgmres_batch_run(const Panel<double> &A, int nv, BatchKrylovWork &kw, const Segments &sg, const double *b,
+                     double *x, double tol, int m, int maxit,
+                     const std::function<void(const double *, double *, int)> &precond,
                      std::vector<vbarms_sinfo> &info, hipStream_t s) {
-    const int64_t n = A.h_rb.empty() ? 0 : A.h_rb.back();
+    const int64_t n = (A.h_rb.empty() ? 0 : A.h_rb.back()) * (int64_t)nv;
     const int ns = sg.nseg;
     kw.ensure(n, m, ns, sg.nchunk);
     double *V = kw.V.p, *Z = kw.Z.p;
@@ -205,7 +207,7 @@ int fgmres_batch_run(const Panel<double> &A, BatchKrylovWork &kw, const Segments
     int it = 0;
     for (;;) {
         // residuals of every system; converged ones stop
-        panel_spmv_ex<double>(A, x, b, V, s);  // V0 = b - A x
+        panel_spmv_ex<double>(A, x, b, V, s, nv);  // V0 = b - A x
         norms(V, beta);
         bool any = false;
         for (int q = 0; q < ns; ++q) {
@@ -239,8 +241,8 @@ int fgmres_batch_run(const Panel<double> &A, BatchKrylovWork &kw, const Segments
         int j = 0;
         for (; j < m && it < maxit; ++j) {
             double *vj = V + (int64_t)j * n, *zj = Z + (int64_t)j * n, *vn = V + (int64_t)(j + 1) * n;
-            precond(vj, zj);
-            panel_spmv<double>(A, zj, vn, s);
+            precond(vj, zj, nv);
+            panel_spmv<double>(A, zj, vn, s, nv);
             seg_dots(sg, kw, n, j + 1, V, vn, h1, ld, s);
             k_seg_update<<<grid_for(n, 256), 256, 0, s>>>(n, sg.rowseg.p, j + 1, V, n, h1, ld, vn);
             VB_LAUNCH_CHECK();

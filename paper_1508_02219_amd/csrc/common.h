@@ -419,7 +419,7 @@ void panel_export(const Panel<T> &a, std::vector<int64_t> &rowptr, std::vector<i
 
 // SpMV y = A x on the panel (spmv.hip); x indexed by sc, y by scalar row.
 template <class T>
-void panel_spmv(const Panel<T> &a, const double *x, double *y, hipStream_t s);
+void panel_spmv(const Panel<T> &a, const double *x, double *y, hipStream_t s, int nv = 1);
 template <class T>
 double panel_spmv_bytes(const Panel<T> &a, bool with_b);
 template <class T>

@@ -28,9 +28,10 @@ struct Level {
     DBuf<int> dpiv;               // [n_is] local row interchanges
     Panel<T> G;                   // L^{-1} P F: IS rows x rest columns
     Panel<T> W;                   // E U^{-1}:   rest rows x IS columns
-    DBuf<double> y;               // apply workspace [n_is]
-    DBuf<double> t;               // apply workspace [n_is]
-    DBuf<double> g, z;            // apply workspace [n_rest]: next level's right-hand side / solution
+    DBuf<double> y;               // apply workspace [n_is] per vector
+    DBuf<double> t;               // apply workspace [n_is] per vector
+    DBuf<double> g, z;            // apply workspace [n_rest] per vector: next level's right-hand side / solution
+    int ws_nv = 0;                // vectors the apply workspaces hold
 };
 
 // An instantiated graph of captured launches (owned; destroyed with its owner).
@@ -68,6 +69,10 @@ struct LastLevel {
     bool use_graph = true;
     LaunchGraph sweeps;
     DBuf<double> gb, gx;          // [n]
+    // the same for several vectors at once (mv_nv vectors, n apart)
+    int mv_nv = 0;
+    LaunchGraph sweeps_mv;
+    DBuf<double> t_mv, gb_mv, gx_mv;
 };
 
 template <class T>
@@ -102,7 +107,7 @@ std::vector<int> graph_compress_host(int n, const std::vector<int64_t> &rp, cons
 void panel_from_csr(int n, const int64_t *rowptr, const int *col, const double *val, const int *perm,
                     const std::vector<int> &bptr, Panel<double> &out, int *err, hipStream_t s);
 template <class T>
-void panel_spmv_ex(const Panel<T> &a, const double *x, const double *b, double *y, hipStream_t s);
+void panel_spmv_ex(const Panel<T> &a, const double *x, const double *b, double *y, hipStream_t s, int nv = 1);
 template <class Tin, class Tout>
 void panel_convert(const Panel<Tin> &src, Panel<Tout> &dst, hipStream_t s);
 
@@ -127,10 +132,10 @@ void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, 
                  hipStream_t s);
 // x = U^{-1} L^{-1} b for the last level (b and x may alias)
 template <class T>
-void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStream_t s);
+void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStream_t s, int nv = 1);
 // x_l = M_l^{-1} b_l recursively from level `lvl` (vectors in the level's numbering)
 template <class T>
-void solve_levels(Factors<T> &f, int lvl, const double *b, double *x, int *err, hipStream_t s);
+void solve_levels(Factors<T> &f, int lvl, const double *b, double *x, int nv, int *err, hipStream_t s);
 
 }  // namespace vb
 
@@ -166,8 +171,12 @@ struct BatchKrylovWork {
 };
 // FGMRES(m) on every segment of A (block diagonal over the segments) in lockstep; info[s]
 // per system.  Returns VBARMS_OK when every system converged.
-int fgmres_batch_run(const Panel<double> &A, BatchKrylovWork &kw, const Segments &sg, const double *b, double *x,
-                     double tol, int m, int maxit, const std::function<void(const double *, double *)> &precond,
+// Lockstep FGMRES over nv copies of the combined system at once: b and x hold nv vectors of
+// A's size one after another, sg segments that long numbering (every system of every
+// vector), and precond(in, out, nv) applies M^{-1} to nv vectors.
+int fgmres_batch_run(const Panel<double> &A, int nv, BatchKrylovWork &kw, const Segments &sg, const double *b,
+                     double *x, double tol, int m, int maxit,
+                     const std::function<void(const double *, double *, int)> &precond,
                      std::vector<vbarms_sinfo> &info, hipStream_t s);
 void gather_perm(int n, const int *perm, const double *src, double *dst, hipStream_t s);
 // VBARMS_NFEAT features of a CSR matrix (host output)

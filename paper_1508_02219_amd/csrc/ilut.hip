@@ -844,7 +844,8 @@ struct SweepRow {
 };
 
 // mode 0: t_i = b_i - sum_k L_ik t_k; mode 1: x_i = D_i^{-1}(t_i - sum_j U_ij x_j).
-// One workgroup per block row of the current level (rows of a level are independent).
+// One workgroup per block row of the current level (rows of a level are independent) and
+// vector (blockIdx.y; b and x hold their vectors ld apart).
 // The lanes of the workgroup are split evenly over the m scalar rows of the block row
 // (a power-of-two group per row, at most 64 lanes), each group strides over the panel
 // columns.  In mode 1 the pivot-block LU factors are staged in LDS and the small
@@ -852,8 +853,10 @@ struct SweepRow {
 template <class T>
 __global__ void __launch_bounds__(kSweepThreads) k_trsv_level(const SweepRow *rows, int mode, const int *sc,
                                                               const T *v, const T *dl, const int *dl_piv,
-                                                              const double *b, double *x) {
+                                                              const double *b, double *x, int64_t ld) {
     __shared__ double sv[VBARMS_MAX_BLOCK];
+    b += blockIdx.y * ld;
+    x += blockIdx.y * ld;
     __shared__ T slu[VBARMS_MAX_BLOCK * VBARMS_MAX_BLOCK];
     __shared__ int spiv[VBARMS_MAX_BLOCK];
     const int t = threadIdx.x;
@@ -1131,75 +1134,89 @@ void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, 
     VB_HIP(hipStreamSynchronize(s));
 }
 
-// the level launches of both sweeps: t = L^{-1} b, then x = U^{-1} t (pivot blocks included)
+// the level launches of both sweeps for nv vectors (n apart): t = L^{-1} b, then
+// x = U^{-1} t (pivot blocks included); t holds nv vectors
 template <class T>
-static void sweep_launches(LastLevel<T> &last, const double *b, double *x, hipStream_t s) {
+static void sweep_launches(LastLevel<T> &last, const double *b, double *x, double *t, int nv, hipStream_t s) {
     const Panel<T> &L = last.L, &U = last.U;
     const SweepRow *lrows = (const SweepRow *)last.d_lrows.p, *urows = (const SweepRow *)last.d_urows.p;
+    const int64_t n = last.A.h_rb.back();
     for (size_t l = 0; l + 1 < last.lptr.size(); ++l) {
         int cnt = last.lptr[l + 1] - last.lptr[l];
-        k_trsv_level<T><<<cnt, kSweepThreads, 0, s>>>(lrows + last.lptr[l], 0, L.sc.p, L.v.p, last.dl.p,
-                                                      last.dl_piv.p, b, last.t.p);
+        k_trsv_level<T><<<dim3(cnt, nv), kSweepThreads, 0, s>>>(lrows + last.lptr[l], 0, L.sc.p, L.v.p, last.dl.p,
+                                                                last.dl_piv.p, b, t, n);
         VB_LAUNCH_CHECK();
     }
     for (size_t l = 0; l + 1 < last.uptr.size(); ++l) {
         int cnt = last.uptr[l + 1] - last.uptr[l];
-        k_trsv_level<T><<<cnt, kSweepThreads, 0, s>>>(urows + last.uptr[l], 1, U.sc.p, U.v.p, last.dl.p,
-                                                      last.dl_piv.p, last.t.p, x);
+        k_trsv_level<T><<<dim3(cnt, nv), kSweepThreads, 0, s>>>(urows + last.uptr[l], 1, U.sc.p, U.v.p, last.dl.p,
+                                                                last.dl_piv.p, t, x, n);
         VB_LAUNCH_CHECK();
     }
 }
 
-// Records the sweeps once on a private stream; the graph reads last.gb and writes last.gx.
+// Records the sweeps for nv vectors once on a private stream into g; the graph reads gb
+// and writes gx (nv vectors each), with t as its workspace.
 template <class T>
-static void capture_sweeps(LastLevel<T> &last) {
-    const int n = last.A.h_rb.back();
-    last.gb.alloc(std::max(n, 1));
-    last.gx.alloc(std::max(n, 1));
+static void capture_sweeps(LastLevel<T> &last, int nv, LaunchGraph &g, DBuf<double> &gb, DBuf<double> &gx,
+                           DBuf<double> &t) {
+    const int64_t n = last.A.h_rb.back();
+    g.reset();
+    gb.alloc((size_t)std::max<int64_t>(n, 1) * nv);
+    gx.alloc((size_t)std::max<int64_t>(n, 1) * nv);
+    if (nv > 1) t.alloc((size_t)std::max<int64_t>(n, 1) * nv);
     hipStream_t cs = nullptr;
     VB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
         try {
-            sweep_launches<T>(last, last.gb.p, last.gx.p, cs);
+            sweep_launches<T>(last, gb.p, gx.p, t.p, nv, cs);
         } catch (...) {
-            hipGraph_t g = nullptr;
-            (void)hipStreamEndCapture(cs, &g);
-            if (g) (void)hipGraphDestroy(g);
+            hipGraph_t gr = nullptr;
+            (void)hipStreamEndCapture(cs, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
             (void)hipStreamDestroy(cs);
             throw;
         }
-        e = hipStreamEndCapture(cs, &last.sweeps.graph);
+        e = hipStreamEndCapture(cs, &g.graph);
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&last.sweeps.exec, last.sweeps.graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
     (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
-        last.sweeps.reset();
+        g.reset();
         fail(VBARMS_ERR_HIP, std::string("capturing the last-level sweeps: ") + hipGetErrorString(e));
     }
 }
 
 template <class T>
-void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStream_t s) {
+void solve_last(LastLevel<T> &last, const double *b, double *x, int *err, hipStream_t s, int nv) {
     (void)err;
     const int p = last.A.p;
-    if (p == 0) return;
+    if (p == 0 || nv < 1) return;
+    const int64_t n = last.A.h_rb.back();
     if (!last.use_graph) {
-        KScope ks(VBARMS_K_TRSV, last.sweep_bytes, s);
-        sweep_launches<T>(last, b, x, s);
+        KScope ks(VBARMS_K_TRSV, last.sweep_bytes * nv, s);
+        if (nv > 1 && last.t_mv.n < (size_t)n * nv) last.t_mv.alloc((size_t)n * nv);
+        sweep_launches<T>(last, b, x, nv == 1 ? last.t.p : last.t_mv.p, nv, s);
         return;
     }
-    const int n = last.A.h_rb.back();
-    if (!last.sweeps.exec) capture_sweeps<T>(last);
-    KScope ks(VBARMS_K_TRSV, last.sweep_bytes, s);
-    if (b != last.gb.p) VB_HIP(hipMemcpyAsync(last.gb.p, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    VB_HIP(hipGraphLaunch(last.sweeps.exec, s));
-    if (x != last.gx.p) VB_HIP(hipMemcpyAsync(x, last.gx.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    LaunchGraph &g = nv == 1 ? last.sweeps : last.sweeps_mv;
+    DBuf<double> &gb = nv == 1 ? last.gb : last.gb_mv, &gx = nv == 1 ? last.gx : last.gx_mv;
+    if (nv == 1 && !g.exec) capture_sweeps<T>(last, 1, g, gb, gx, last.t);
+    if (nv > 1 && (!g.exec || last.mv_nv != nv)) {
+        capture_sweeps<T>(last, nv, g, gb, gx, last.t_mv);
+        last.mv_nv = nv;
+    }
+    KScope ks(VBARMS_K_TRSV, last.sweep_bytes * nv, s);
+    const size_t bytes = sizeof(double) * (size_t)n * nv;
+    if (b != gb.p) VB_HIP(hipMemcpyAsync(gb.p, b, bytes, hipMemcpyDeviceToDevice, s));
+    VB_HIP(hipGraphLaunch(g.exec, s));
+    if (x != gx.p) VB_HIP(hipMemcpyAsync(x, gx.p, bytes, hipMemcpyDeviceToDevice, s));
 }
 
 template void factor_last<double>(LastLevel<double> &, double, double, int, IlutHint &, int *, hipStream_t);
 template void factor_last<float>(LastLevel<float> &, double, double, int, IlutHint &, int *, hipStream_t);
-template void solve_last<double>(LastLevel<double> &, const double *, double *, int *, hipStream_t);
-template void solve_last<float>(LastLevel<float> &, const double *, double *, int *, hipStream_t);
+template void solve_last<double>(LastLevel<double> &, const double *, double *, int *, hipStream_t, int);
+template void solve_last<float>(LastLevel<float> &, const double *, double *, int *, hipStream_t, int);
 
 }  // namespace vb

@@ -948,8 +948,7 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
         VB_LAUNCH_CHECK();
     }
     panel_compact<T>(S, nullptr, skeep.p, nullptr, nrest, nullptr, L.h_rest_rb, L.h_rest_rb, next, s);
-    L.y.alloc(std::max(L.n_is, 1));
-    L.t.alloc(std::max(L.n_is, 1));
+    L.ws_nv = 0;  // apply workspaces are sized by the first application
 }
 
 template void factor_level<double>(Level<double> &, Panel<double> &&, int, double, int, int, int, double,

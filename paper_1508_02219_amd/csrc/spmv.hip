@@ -10,51 +10,79 @@ namespace vb {
 
 namespace {
 
-template <class T, int TG>
+// NV vectors per launch row of the grid (blockIdx.y selects the group of NV vectors, each
+// ld apart): every matrix value and column index is loaded once for the NV products.  The
+// sum of every vector keeps the column order of the single-vector product.
+template <class T, int TG, int NV>
 __global__ void __launch_bounds__(256) k_spmv(int64_t n, const int *__restrict__ rowblk, const int *__restrict__ rb,
                                               const int64_t *__restrict__ wp, const int64_t *__restrict__ vp,
                                               const int *__restrict__ sc, const T *__restrict__ v,
                                               const double *__restrict__ x, const double *__restrict__ b,
-                                              double *__restrict__ y) {
+                                              double *__restrict__ y, int nv, int64_t ld) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t row = gid / TG;
     int lane = (int)(gid % TG);
-    double acc = 0.0;
+    const int v0 = blockIdx.y * NV;
+    const int cnt = nv - v0 < NV ? nv - v0 : NV;
+    const int64_t base = (int64_t)v0 * ld;
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
     if (row < n) {
         int I = rowblk[row];
         int rl = (int)(row - rb[I]);
         int64_t W = wp[I + 1] - wp[I];
         const T *a = v + vp[I] + rl * W;
         const int *c = sc + wp[I];
-        for (int64_t j = lane; j < W; j += TG) acc += (double)a[j] * x[c[j]];
+        const double *xv = x + base;
+        for (int64_t j = lane; j < W; j += TG) {
+            const double aj = (double)a[j];
+            const int cj = c[j];
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+                if (q < cnt) acc[q] += aj * xv[q * ld + cj];
+        }
     }
 #pragma unroll
-    for (int off = TG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, TG);
-    if (row < n && lane == 0) y[row] = b ? b[row] - acc : acc;
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+        for (int off = TG / 2; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, TG);
+    if (row < n && lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            if (q < cnt) {
+                const int64_t o = base + q * ld + row;
+                y[o] = b ? b[o] - acc[q] : acc[q];
+            }
+}
+
+template <class T, int TG>
+void launch_spmv(const Panel<T> &a, int64_t n, const double *x, const double *b, double *y, int nv, int64_t ld,
+                 hipStream_t s) {
+    if (nv == 1) {
+        k_spmv<T, TG, 1><<<grid_for(n * TG, 256), 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p,
+                                                               x, b, y, 1, ld);
+    } else {
+        const dim3 grid(grid_for(n * TG, 256), (unsigned)((nv + 3) / 4));
+        k_spmv<T, TG, 4><<<grid, 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p, x, b, y, nv, ld);
+    }
+    VB_LAUNCH_CHECK();
 }
 
 }  // namespace
 
-// Lanes per scalar row: as many lanes as the autotuner picked for this matrix.
+// Lanes per scalar row: as many lanes as the autotuner picked for this matrix.  nv vectors
+// (x, b and y each hold nv vectors of n entries, n apart) share the launch.
 template <class T>
-void panel_spmv_ex(const Panel<T> &a, const double *x, const double *b, double *y, hipStream_t s) {
+void panel_spmv_ex(const Panel<T> &a, const double *x, const double *b, double *y, hipStream_t s, int nv) {
     int64_t n = a.h_rb.empty() ? 0 : a.h_rb.back();
-    if (n == 0) return;
+    if (n == 0 || nv < 1) return;
     switch (a.tg) {
-    case 4:
-        k_spmv<T, 4><<<grid_for(n * 4, 256), 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p, x, b, y);
-        break;
-    case 16:
-        k_spmv<T, 16><<<grid_for(n * 16, 256), 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p, x, b, y);
-        break;
-    case 32:
-        k_spmv<T, 32><<<grid_for(n * 32, 256), 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p, x, b, y);
-        break;
-    default:
-        k_spmv<T, 8><<<grid_for(n * 8, 256), 256, 0, s>>>(n, a.rowblk.p, a.rb.p, a.wp.p, a.vp.p, a.sc.p, a.v.p, x, b, y);
-        break;
+    case 4: launch_spmv<T, 4>(a, n, x, b, y, nv, n, s); break;
+    case 16: launch_spmv<T, 16>(a, n, x, b, y, nv, n, s); break;
+    case 32: launch_spmv<T, 32>(a, n, x, b, y, nv, n, s); break;
+    default: launch_spmv<T, 8>(a, n, x, b, y, nv, n, s); break;
     }
-    VB_LAUNCH_CHECK();
 }
 
 // Times the product with 4, 8, 16 and 32 lanes per scalar row on this matrix (one warm-up
@@ -74,9 +102,9 @@ int autotune_spmv(Panel<T> &a, hipStream_t s) {
     int best_tg = 8;
     for (int tg : {4, 8, 16, 32}) {
         a.tg = tg;
-        panel_spmv_ex<T>(a, x.p, nullptr, y.p, s);
+        panel_spmv_ex<T>(a, x.p, nullptr, y.p, s, 1);
         VB_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < 5; ++r) panel_spmv_ex<T>(a, x.p, nullptr, y.p, s);
+        for (int r = 0; r < 5; ++r) panel_spmv_ex<T>(a, x.p, nullptr, y.p, s, 1);
         VB_HIP(hipEventRecord(e1, s));
         VB_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -103,16 +131,16 @@ double panel_spmv_bytes(const Panel<T> &a, bool with_b) {
 }
 
 template <class T>
-void panel_spmv(const Panel<T> &a, const double *x, double *y, hipStream_t s) {
-    panel_spmv_ex<T>(a, x, nullptr, y, s);
+void panel_spmv(const Panel<T> &a, const double *x, double *y, hipStream_t s, int nv) {
+    panel_spmv_ex<T>(a, x, nullptr, y, s, nv);
 }
 
 template double panel_spmv_bytes<double>(const Panel<double> &, bool);
 template double panel_spmv_bytes<float>(const Panel<float> &, bool);
-template void panel_spmv<double>(const Panel<double> &, const double *, double *, hipStream_t);
-template void panel_spmv<float>(const Panel<float> &, const double *, double *, hipStream_t);
-template void panel_spmv_ex<double>(const Panel<double> &, const double *, const double *, double *, hipStream_t);
-template void panel_spmv_ex<float>(const Panel<float> &, const double *, const double *, double *, hipStream_t);
+template void panel_spmv<double>(const Panel<double> &, const double *, double *, hipStream_t, int);
+template void panel_spmv<float>(const Panel<float> &, const double *, double *, hipStream_t, int);
+template void panel_spmv_ex<double>(const Panel<double> &, const double *, const double *, double *, hipStream_t, int);
+template void panel_spmv_ex<float>(const Panel<float> &, const double *, const double *, double *, hipStream_t, int);
 template int autotune_spmv<double>(Panel<double> &, hipStream_t);
 template int autotune_spmv<float>(Panel<float> &, hipStream_t);
 

@@ -41,22 +41,23 @@ def _residual(s, x):
     return np.linalg.norm(s.b - a @ x) / np.linalg.norm(s.b)
 
 
-@pytest.mark.parametrize("tau,levels,t", [(0.8, 2, 1e-3), (1.0, 0, 1e-3), (0.8, 3, 1e-4)])
-def test_batch_factors_are_the_individual_factors(vb, tau, levels, t):
+@pytest.mark.parametrize("tau,levels,t,groups", [(0.8, 2, 1e-3, 0), (1.0, 0, 1e-3, 0), (0.8, 3, 1e-4, 0),
+                                                 (0.8, 2, 1e-3, 16), (1.0, 3, 1e-4, 32)])
+def test_batch_factors_are_the_individual_factors(vb, tau, levels, t, groups):
     """M^{-1} of the combined system applied to a concatenated vector equals, bit for bit,
-    every system's own M^{-1} applied to its part."""
+    every system's own M^{-1} applied to its part (groups never span two systems)."""
     import torch
     systems = _systems()
-    _say(f"[case] batch of {len(systems)} systems tau={tau} levels={levels} t={t}")
+    _say(f"[case] batch of {len(systems)} systems tau={tau} levels={levels} t={t} group_rows={groups}")
     bs = vb.BatchSolver()
-    off = bs.factor([vb.csr_to_device(s) for s in systems], tau, levels, t)
+    off = bs.factor([vb.csr_to_device(s) for s in systems], tau, levels, t, group_rows=groups)
     assert list(np.diff(off)) == [s.n for s in systems]
     x = np.random.default_rng(1).standard_normal(int(off[-1]))
     y = bs.handle().apply(torch.as_tensor(x, device="cuda")).cpu().numpy()
     for q, s in enumerate(systems):
         sv = vb.Solver()
         sv.compress(*vb.csr_to_device(s), tau)
-        sv.factor(levels, t)
+        sv.factor(levels, t, group_rows=groups)
         yq = sv.apply(torch.as_tensor(x[off[q]:off[q + 1]].copy(), device="cuda")).cpu().numpy()
         assert np.array_equal(y[off[q]:off[q + 1]], yq), f"system {q}"
         sv.close()
@@ -118,4 +119,26 @@ def test_batch_argument_errors(vb):
     with pytest.raises(vb.VbarmsError) as e:
         bs.factor([], 0.8, 1, 1e-3)
     assert e.value.code == vb.ERR_ARG
+    bs.close()
+
+
+def test_batch_right_hand_sides_in_lockstep_equal_one_at_a_time(vb):
+    """Several right-hand sides go through one lockstep FGMRES (multi-vector SpMV and
+    preconditioner); every solution equals, bit for bit, the solve of its right-hand side
+    alone, and so do the iteration counts."""
+    import torch
+    systems = _systems()[:4]
+    bs = vb.BatchSolver()
+    off = bs.factor([vb.csr_to_device(s) for s in systems], 0.8, 2, 1e-3, group_rows=16)
+    N = int(off[-1])
+    B = np.random.default_rng(21).standard_normal((5, N))
+    B[3, off[1]:off[2]] = 0.0
+    X, info = bs.solve(torch.as_tensor(B, device="cuda"), tol=1e-8, restart=15)
+    X = X.cpu().numpy()
+    for r in range(5):
+        Xr, ir = bs.solve(torch.as_tensor(B[r:r + 1].copy(), device="cuda"), tol=1e-8, restart=15)
+        assert np.array_equal(X[r], Xr.cpu().numpy()[0]), f"right-hand side {r}"
+        for q in range(len(systems)):
+            assert info[r][q].iters == ir[0][q].iters and info[r][q].status == ir[0][q].status
+            assert info[r][q].true_relres == ir[0][q].true_relres
     bs.close()

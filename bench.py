@@ -7,7 +7,8 @@ values with cell Peclet numbers LogUniform(0.1, 100); tau = 1 (exact node blocks
 levels whose independent sets are groups of supernodes of up to 32 rows, drop tolerance
 1e-4, FGMRES(60) to a true relative residual of 1e-8, b = A 1.
 `--workload grid40` runs the 40^3 five-unknown workload instead (n = 320,000, 10% block
-perturbation, tau = 0.8, 3 levels, FGMRES(50)).
+perturbation, tau = 0.8, 3 levels with groups of up to 16 rows, FGMRES(50)); `--batch`
+runs 256 systems of that recipe with the same settings.
 
 One step = the whole hot path from the device-resident CSR: compress (Sec. 2.1), factor
 (Sec. 3, all levels and the last-level block ILUT), solve (FGMRES with the
@@ -46,7 +47,7 @@ WORKLOADS = {
     "grid40": dict(desc="40^3 nodes, 14-neighbour random stencil, 5 unknowns per node, 10% block perturbation",
                    make=lambda side: __import__("paper_1508_02219_amd.synth", fromlist=["x"]).grid_system(
                        side, side, side, 5, "14rand", 0.10, seed=2),
-                   side=40, sample_side=40, tau=0.8, levels=3, droptol=1e-4, restart=50, group_rows=0),
+                   side=40, sample_side=40, tau=0.8, levels=3, droptol=1e-4, restart=50, group_rows=16),
 }
 
 
@@ -65,7 +66,7 @@ def _sources_sha256():
     return h.hexdigest()
 
 
-def _traffic(kernel, workload, group_rows):
+def _traffic(kernel, workload, group_rows, weighted):
     """HBM bytes per dispatch of `kernel` from the committed counter record (FETCH_SIZE and
     WRITE_SIZE scaled by the copy calibration), or None when no record matches this kernel,
     this workload and the current sources."""
@@ -74,7 +75,7 @@ def _traffic(kernel, workload, group_rows):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if (rec.get("kernel") != kernel or workload != "upwind74" or group_rows != 32
+    if (rec.get("kernel") != kernel or workload != "upwind74" or group_rows != 32 or weighted
             or rec.get("sources_sha256") != _sources_sha256()):
         return None
     return rec["bytes_per_dispatch"]
@@ -196,7 +197,7 @@ def _batch_bench(args, V, torch):
     import numpy as np
 
     count, nrhs, tau, levels, droptol, restart = args.batch, 16, 0.8, 3, 1e-4, 50
-    group_rows = max(args.group_rows, 0)
+    group_rows = WORKLOADS["grid40"]["group_rows"] if args.group_rows < 0 else args.group_rows
     t0 = time.perf_counter()
     systems = _batch_systems(count)
     print(f"[bench] generated {count} systems (n = {sum(s.n for s in systems)}) in "
@@ -297,6 +298,8 @@ def main() -> int:
     ap.add_argument("--group-rows", type=int, default=-1, metavar="K",
                     help="groups of supernodes in the independent sets, at most K rows each (0: one supernode; "
                          "default: the workload's setting)")
+    ap.add_argument("--weighted-is", action="store_true",
+                    help="visit supernodes by the weighted order in the independent sets (default: natural order)")
     ap.add_argument("--comparators", type=int, default=0, metavar="SIDE",
                     help="instead of the benchmark, compare VBARMS with block ILUT alone (VBILUT, levels = 0) and "
                          "with pointwise ILUT (1x1 blocks, levels = 0) on a SIDE^3 grid of the workload's recipe")
@@ -328,6 +331,7 @@ def main() -> int:
     wl = WORKLOADS[args.workload]
     tau, levels, droptol, restart = wl["tau"], wl["levels"], wl["droptol"], wl["restart"]
     group_rows = wl["group_rows"] if args.group_rows < 0 else args.group_rows
+    is_order = V.IS_WEIGHTED if args.weighted_is else V.IS_NATURAL
     if args.comparators:
         return _comparators(wl, args.comparators, V, torch)
     system = wl["make"](wl["side"])
@@ -339,7 +343,7 @@ def main() -> int:
 
     def step(prec):
         _, _, st = sv.compress(rp, ci, va, tau)
-        sv.factor(levels, droptol, 1, V.F32 if prec == "f32" else V.F64, V.IS_NATURAL, group_rows)
+        sv.factor(levels, droptol, 1, V.F32 if prec == "f32" else V.F64, is_order, group_rows)
         x, info = sv.solve(b, tol=TOL, restart=restart, maxit=MAXIT)
         return st, info
 
@@ -407,7 +411,7 @@ def main() -> int:
                 "frac": None if achieved is None else round(achieved / HBM_PEAK_GBPS, 6), "traffic": None}
     if dom == "ilut_wave":
         roofline["traffic"] = _traffic("k_ilut_wave<float>" if head == "f32" else "k_ilut_wave<double>",
-                                       args.workload, group_rows)
+                                       args.workload, group_rows, args.weighted_is)
 
     def summary(prec):
         r = runs[prec]
@@ -439,6 +443,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": system.n, "nnz": system.nnz, "blocks": R["st"].nblocks,
                    "tau": tau, "levels": levels, "droptol": droptol, "group_rows": group_rows,
+                   "independent_set_order": "weighted" if args.weighted_is else "natural",
                    "krylov": f"FGMRES({restart})", "tol": TOL, "rhs": "A*1"},
         "runs": {p: summary(p) for p in precs},
         "device_memory_GiB": {"peak_live": round(mem["peak"] / 2**30, 2), "cached": round(mem["cached"] / 2**30, 2),

@@ -8,7 +8,8 @@ levels whose independent sets are groups of supernodes of up to 32 rows, drop to
 1e-4, FGMRES(60) to a true relative residual of 1e-8, b = A 1.
 `--workload grid40` runs the 40^3 five-unknown workload instead (n = 320,000, 10% block
 perturbation, tau = 0.8, 3 levels with groups of up to 16 rows, FGMRES(50)); `--batch`
-runs 256 systems of that recipe with the same settings.
+runs 256 systems of that recipe (one supernode per group there: the host greedy over all
+systems of a chunk costs more than the groups save).
 
 One step = the whole hot path from the device-resident CSR: compress (Sec. 2.1), factor
 (Sec. 3, all levels and the last-level block ILUT), solve (FGMRES with the
@@ -197,7 +198,7 @@ def _batch_bench(args, V, torch):
     import numpy as np
 
     count, nrhs, tau, levels, droptol, restart = args.batch, 16, 0.8, 3, 1e-4, 50
-    group_rows = WORKLOADS["grid40"]["group_rows"] if args.group_rows < 0 else args.group_rows
+    group_rows = 0 if args.group_rows < 0 else args.group_rows  # groups did not pay off on the batch
     t0 = time.perf_counter()
     systems = _batch_systems(count)
     print(f"[bench] generated {count} systems (n = {sum(s.n for s in systems)}) in "

@@ -195,6 +195,11 @@ int vbarms_apply(vbarms_t h, const double *x, double *y);
 /* y = A x with the compressed matrix (original numbering, DEVICE vectors). */
 int vbarms_spmv(vbarms_t h, const double *x, double *y);
 
+/* Overrides the lanes per scalar row (4, 8, 16 or 32) that compression picked by timing
+ * the product.  Every choice computes the same product up to rounding order.  Errors:
+ * STATE before compress, ARG for another value. */
+int vbarms_set_spmv_lanes(vbarms_t h, int32_t lanes);
+
 /* y = A x exactly as vbarms_spmv, for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  It
  * allocates nothing: the permuted copies of x and y live in a fixed array of

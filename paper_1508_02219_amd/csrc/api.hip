@@ -569,6 +569,17 @@ int vbarms_spmv(vbarms_t h, const double *x, double *y) {
     });
 }
 
+int vbarms_set_spmv_lanes(vbarms_t h, int32_t lanes) {
+    return guarded(h, [&] {
+        if (!h->have_A) fail(VBARMS_ERR_STATE, "no compressed matrix");
+        if (lanes != 4 && lanes != 8 && lanes != 16 && lanes != 32)
+            fail(VBARMS_ERR_ARG, "lanes must be 4, 8, 16 or 32");
+        h->A.tg = lanes;
+        h->stats.spmv_lanes = lanes;
+        return VBARMS_OK;
+    });
+}
+
 int vbarms_spmv_noalloc(vbarms_t h, const double *x, double *y) {
     return guarded(h, [&] {
         if (!h->have_A) fail(VBARMS_ERR_STATE, "no compressed matrix");

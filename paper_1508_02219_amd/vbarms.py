@@ -114,6 +114,7 @@ SIGNATURES = {
     "vbarms_level_info": (C.c_int, [_P, C.c_int32, _P]),
     "vbarms_level_is": (C.c_int, [_P, C.c_int32, _P]),
     "vbarms_level_groups": (C.c_int, [_P, C.c_int32, _P]),
+    "vbarms_set_spmv_lanes": (C.c_int, [_P, C.c_int32]),
     "vbarms_level_scaling": (C.c_int, [_P, C.c_int32, _P, _P]),
     "vbarms_matrix_dims": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
     "vbarms_matrix_get": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P]),
@@ -270,6 +271,11 @@ class Solver:
         y = torch.empty_like(x) if out is None else out
         self._check(lib().vbarms_apply(self.h, _dev_ptr(x, torch.float64), _dev_ptr(y, torch.float64)))
         return y
+
+    def set_spmv_lanes(self, lanes):
+        """Lanes per scalar row of the product kernel (4, 8, 16 or 32), overriding the pick of
+        the autotuner."""
+        self._check(lib().vbarms_set_spmv_lanes(self.h, int(lanes)))
 
     def spmv(self, x, out=None):
         torch = self._torch

@@ -489,9 +489,14 @@ def test_spmv_lanes_autotuned_and_product_exact(vb):
         _say(f"[case] {s.name}: autotuned lanes per row {lanes}")
         assert lanes in (4, 8, 16, 32)
         x = np.random.default_rng(2).standard_normal(s.n)
-        ax = sv.spmv(torch.as_tensor(x, device="cuda")).cpu().numpy()
         a = sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n))
-        assert np.abs(ax - a @ x).max() <= 1e-13 * np.abs(a @ x).max()
+        for choice in (lanes, 4, 8, 16, 32):  # the pick, then every lane count
+            sv.set_spmv_lanes(choice)
+            ax = sv.spmv(torch.as_tensor(x, device="cuda")).cpu().numpy()
+            assert np.abs(ax - a @ x).max() <= 1e-13 * np.abs(a @ x).max(), choice
+        with pytest.raises(vb.VbarmsError) as e:
+            sv.set_spmv_lanes(0)
+        assert e.value.code == vb.ERR_ARG
 
 
 def test_zz_report_exact_share():

@@ -281,6 +281,72 @@ def _batch_bench(args, V, torch):
     return 0
 
 
+def _learned_bench(args, V, torch):
+    """Learned parameter selection on held-out matrices of the training recipe at 74^3
+    nodes (n = 1.2M to 2.4M): the network is trained on the stored sweeps of the 20^3-34^3
+    training matrices with the library's kernels, then each held-out matrix is solved with
+    the predicted (tau, per-level t) in FP64 and with FP32 factors, with the defaults in
+    FP64 (the plain method) and with the best constant setting of the sweeps in FP64.  A
+    setting that does not converge within the sweeps' iteration limit is charged its run
+    plus the defaults' run, as the method falls back to the defaults."""
+    import math
+
+    import numpy as np
+    from paper_1508_02219_amd import learned as Lr
+
+    meta, recs = Lr.load_dataset(os.path.join(ROOT, "paper_1508_02219_amd", "data", "x4_training_sweeps.json"))
+    X = np.array([r["features"] for r in recs], np.float32)
+    Y = np.array([Lr.target(r["label"]) for r in recs], np.float32)
+    pred = Lr.Predictor(seed=0)
+    pred.fit(X, Y, epochs=200, lr=2e-3, batch=32)
+    (ctau, ctol), _ = Lr.best_constant(recs)
+    rows = []
+    for k in range(args.learned):
+        r = Lr.recipe(9000 + k, side_range=(74, 74))
+        t0 = time.perf_counter()
+        s = Lr.make_system(r)
+        print(f"[learned] {s.name} n={s.n} ell={r['ell']} pe={r['pe']:.2f} aniso={r['aniso']:.1f} "
+              f"(generated in {time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+        dev = V.csr_to_device(s)
+        b = torch.as_tensor(s.b, device="cuda")
+        sv = V.Solver()
+        (tau, tols), = pred.predict(sv.features(*dev))
+
+        def measure(tau_, tols_, prec):
+            Lr.run_once(sv, dev, b, tau_, tols_, precision=prec)  # warm-up of this setting
+            return Lr.run_once(sv, dev, b, tau_, tols_, precision=prec)
+
+        dflt = measure(Lr.DEFAULT_TAU, Lr.DEFAULT_TOL, V.F64)
+        res = {"defaults_f64": dflt, "learned_f64": measure(tau, tols, V.F64),
+               "learned_f32": measure(tau, tols, V.F32), "constant_f64": measure(ctau, ctol, V.F64)}
+        sv.close()
+        row = {"n": s.n, "pe": round(r["pe"], 2), "ell": r["ell"], "predicted_tau": round(tau, 3),
+               "predicted_t": [float(f"{t:.2e}") for t in tols]}
+        for key, rr in res.items():
+            ms = rr.ms if rr.ok else (rr.ms + dflt.ms if dflt.ok else math.inf)
+            row[key] = {"ms": round(ms, 1), "iters": rr.iters, "converged": bool(rr.ok)}
+        rows.append(row)
+        print(f"[learned] {json.dumps(row)}", file=sys.stderr, flush=True)
+    solved = [r for r in rows if r["defaults_f64"]["converged"]]
+
+    def gm(a, b):
+        v = [r[a]["ms"] / r[b]["ms"] for r in solved if math.isfinite(r[a]["ms"]) and math.isfinite(r[b]["ms"])]
+        return round(float(np.exp(np.mean(np.log(v)))), 3) if v else None
+
+    out = {"metric": "time-to-solve, learned (tau, per-level t) vs the defaults (FP64 plain) and vs the best "
+                     "constant setting", "unit": "x (geometric mean of time ratios)", "n_gpus": 1,
+           "data": "synthetic", "config": {"workload": "held-out matrices of the learned-selection recipe at 74^3 "
+                                                       "nodes", "levels": Lr.LEVELS, "restart": Lr.RESTART,
+                                           "maxit": Lr.MAXIT, "tol": Lr.RTOL, "defaults": [Lr.DEFAULT_TAU, Lr.DEFAULT_TOL],
+                                           "best_constant": [ctau, ctol], "training_matrices": len(recs)},
+           "matrices": rows, "solved_by_defaults": len(solved),
+           "speedup_learned_f64_vs_defaults_f64": gm("defaults_f64", "learned_f64"),
+           "speedup_learned_f32_vs_defaults_f64": gm("defaults_f64", "learned_f32"),
+           "speedup_learned_f64_vs_constant_f64": gm("constant_f64", "learned_f64")}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +365,9 @@ def main() -> int:
     ap.add_argument("--group-rows", type=int, default=-1, metavar="K",
                     help="groups of supernodes in the independent sets, at most K rows each (0: one supernode; "
                          "default: the workload's setting)")
+    ap.add_argument("--learned", type=int, default=0, metavar="K",
+                    help="instead of the benchmark, evaluate the learned parameter selection on K held-out "
+                         "matrices of its recipe at 74^3 nodes")
     ap.add_argument("--weighted-is", action="store_true",
                     help="visit supernodes by the weighted order in the independent sets (default: natural order)")
     ap.add_argument("--comparators", type=int, default=0, metavar="SIDE",
@@ -329,6 +398,8 @@ def main() -> int:
         return 0
     if args.batch:
         return _batch_bench(args, V, torch)
+    if args.learned:
+        return _learned_bench(args, V, torch)
     wl = WORKLOADS[args.workload]
     tau, levels, droptol, restart = wl["tau"], wl["levels"], wl["droptol"], wl["restart"]
     group_rows = wl["group_rows"] if args.group_rows < 0 else args.group_rows

@@ -72,11 +72,12 @@ def make_system(r, side=None):
                                anisotropy=r["aniso"], perturb=r["pert"], seed=r["seed"])
 
 
-def run_once(sv: V.Solver, dev, b, tau, tols, levels=LEVELS, restart=RESTART, rtol=RTOL, maxit=MAXIT) -> RunResult:
+def run_once(sv: V.Solver, dev, b, tau, tols, levels=LEVELS, restart=RESTART, rtol=RTOL, maxit=MAXIT,
+             precision=V.F64) -> RunResult:
     tols = tuple(float(t) for t in np.broadcast_to(np.asarray(tols, float), (levels + 1,)))
     try:
         sv.compress(*dev, tau)
-        sv.factor(levels, list(tols))
+        sv.factor(levels, list(tols), precision=precision)
         _, info = sv.solve(b, tol=rtol, restart=restart, maxit=maxit)
     except V.VbarmsError:
         return RunResult(tau, tols, False, 0, math.inf, math.inf)

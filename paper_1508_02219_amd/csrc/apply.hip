@@ -18,19 +18,30 @@ namespace {
 constexpr int kTG = 8;
 
 template <class T>
-__global__ void k_lvl_down(int nis, const int *is_rows, const int *is_rb, const double *s1, const double *b,
-                           int64_t ldb, const T *dlu, const int64_t *dlu_off, const int *dpiv, double *y,
-                           int64_t ldy) {
+__global__ void __launch_bounds__(64) k_lvl_down(int nis, const int *is_rows, const int *is_rb, const double *s1,
+                                                 const double *b, int64_t ldb, const T *dlu, const int64_t *dlu_off,
+                                                 const int *dperm, double *y, int64_t ldy) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nis) return;
     b += blockIdx.y * ldb;
     y += blockIdx.y * ldy;
     const int m = is_rb[i + 1] - is_rb[i];
     const int *rows = is_rows + is_rb[i];
-    double x[VBARMS_MAX_BLOCK];
-    for (int r = 0; r < m; ++r) x[r] = s1[rows[r]] * b[rows[r]];
-    dev_lu_fwd<T, double>(m, dlu + dlu_off[i], dpiv + is_rb[i], x);
-    for (int r = 0; r < m; ++r) y[is_rb[i] + r] = x[r];
+    const int *pm = dperm + is_rb[i];
+    double x[VBARMS_MAX_BLOCK];  // P (S1 b) of the block, the exchanges applied while loading
+#pragma unroll
+    for (int r = 0; r < VBARMS_MAX_BLOCK; ++r) {
+        if (r < m) {
+            const int row = rows[pm[r]];
+            x[r] = s1[row] * b[row];
+        } else {
+            x[r] = 0.0;
+        }
+    }
+    reg_l_fwd<T, double, VBARMS_MAX_BLOCK>(m, dlu + dlu_off[i], x);
+#pragma unroll
+    for (int r = 0; r < VBARMS_MAX_BLOCK; ++r)
+        if (r < m) y[is_rb[i] + r] = x[r];
 }
 
 // out[rr] = s1[row(rr)] base[row(rr)] - sum_c P[rr, c] v[sc[c]], with row(rr) = rows[rr]
@@ -70,8 +81,9 @@ __global__ void __launch_bounds__(256) k_lvl_spmv(int64_t nrows, const int *rowb
 }
 
 template <class T>
-__global__ void k_lvl_up(int nis, const int *is_rows, const int *is_rb, const double *s2, const T *dlu,
-                         const int64_t *dlu_off, const double *t, int64_t ldt, double *x, int64_t ldx) {
+__global__ void __launch_bounds__(64) k_lvl_up(int nis, const int *is_rows, const int *is_rb, const double *s2,
+                                               const T *dlu, const int64_t *dlu_off, const double *t, int64_t ldt,
+                                               double *x, int64_t ldx) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nis) return;
     t += blockIdx.y * ldt;
@@ -79,9 +91,12 @@ __global__ void k_lvl_up(int nis, const int *is_rows, const int *is_rb, const do
     const int m = is_rb[i + 1] - is_rb[i];
     const int *rows = is_rows + is_rb[i];
     double u[VBARMS_MAX_BLOCK];
-    for (int r = 0; r < m; ++r) u[r] = t[is_rb[i] + r];
-    dev_lu_bwd<T, double>(m, dlu + dlu_off[i], u);
-    for (int r = 0; r < m; ++r) x[rows[r]] = s2[rows[r]] * u[r];
+#pragma unroll
+    for (int r = 0; r < VBARMS_MAX_BLOCK; ++r) u[r] = r < m ? t[is_rb[i] + r] : 0.0;
+    reg_lu_bwd<T, double, VBARMS_MAX_BLOCK>(m, dlu + dlu_off[i], u);
+#pragma unroll
+    for (int r = 0; r < VBARMS_MAX_BLOCK; ++r)
+        if (r < m) x[rows[r]] = s2[rows[r]] * u[r];
 }
 
 __global__ void k_lvl_rest_out(int64_t nrest_rows, const int *rest_rows, const double *s2, const double *z,
@@ -114,7 +129,7 @@ void solve_levels(Factors<T> &f, int lvl, const double *b, double *x, int nv, in
     const unsigned vy = (unsigned)nv;
     if (L.nis > 0) {
         k_lvl_down<T><<<dim3(grid_for(L.nis, 64), vy), 64, 0, s>>>(L.nis, L.is_rows.p, L.is_rb.p, L.s1.p, b, n,
-                                                                    L.dlu.p, L.dlu_off.p, L.dpiv.p, L.y.p, nis);
+                                                                    L.dlu.p, L.dlu_off.p, L.dperm.p, L.y.p, nis);
         VB_LAUNCH_CHECK();
     }
     if (L.n_rest > 0) {

@@ -349,6 +349,35 @@ __device__ inline void dev_lu_bwd(int m, const T *lu, V *x) {
         x[r] = s / V(lu[r * m + r]);
     }
 }
+// Register versions for vectors of up to MAXM entries: the loops are unrolled to MAXM with
+// guards, so the vector never leaves registers; operations and order are those above.
+// x <- L^{-1} x (unit lower triangle; the row exchanges are applied beforehand)
+template <class T, class V, int MAXM>
+__device__ inline void reg_l_fwd(int m, const T *lu, V (&x)[MAXM]) {
+#pragma unroll
+    for (int r = 0; r < MAXM; ++r) {
+        if (r < m) {
+            V s = x[r];
+#pragma unroll
+            for (int q = 0; q < r; ++q) s = s - V(lu[r * m + q]) * x[q];
+            x[r] = s;
+        }
+    }
+}
+// x <- U^{-1} x
+template <class T, class V, int MAXM>
+__device__ inline void reg_lu_bwd(int m, const T *lu, V (&x)[MAXM]) {
+#pragma unroll
+    for (int r = MAXM - 1; r >= 0; --r) {
+        if (r < m) {
+            V s = x[r];
+#pragma unroll
+            for (int q = r + 1; q < MAXM; ++q)
+                if (q < m) s = s - V(lu[r * m + q]) * x[q];
+            x[r] = s / V(lu[r * m + r]);
+        }
+    }
+}
 // row vector e <- e U^{-1}, e strided by `st`
 template <class T>
 __device__ inline void dev_row_solve_u(int m, const T *lu, T *e, int st) {

@@ -26,6 +26,7 @@ struct Level {
     DBuf<T> dlu;                  // LU of the IS pivot blocks, concatenated
     DBuf<int64_t> dlu_off;        // [nis+1]
     DBuf<int> dpiv;               // [n_is] local row interchanges
+    DBuf<int> dperm;              // [n_is] the interchanges as a permutation: row r of P x is x[dperm[r]]
     Panel<T> G;                   // L^{-1} P F: IS rows x rest columns
     Panel<T> W;                   // E U^{-1}:   rest rows x IS columns
     DBuf<double> y;               // apply workspace [n_is] per vector

@@ -159,21 +159,6 @@ __global__ void k_gepp(int nis, const int *is_list, const int *rb, const int64_t
     }
 }
 
-// x <- L^{-1} x (unit lower triangle of an LU) for a vector of up to MAXM entries held in
-// registers; the operations and their order are those of dev_lu_fwd after its exchanges.
-template <class T, int MAXM>
-__device__ inline void reg_l_fwd(int m, const T *lu, T (&x)[MAXM]) {
-#pragma unroll
-    for (int r = 0; r < MAXM; ++r) {
-        if (r < m) {
-            T s = x[r];
-#pragma unroll
-            for (int q = 0; q < r; ++q) s = s - lu[r * m + q] * x[q];
-            x[r] = s;
-        }
-    }
-}
-
 // G = L^{-1} P F: one lane per panel column of an independent block row (F columns only)
 template <class T>
 __global__ void __launch_bounds__(128) k_compute_g(int p, int64_t nw, const int64_t *wp, const int64_t *vp, const int *rb, const int *sc,
@@ -194,7 +179,7 @@ __global__ void __launch_bounds__(128) k_compute_g(int p, int64_t nw, const int6
     T x[VBARMS_MAX_BLOCK];  // P applied while loading
 #pragma unroll
     for (int r = 0; r < VBARMS_MAX_BLOCK; ++r) x[r] = r < m ? a[(int64_t)pm[r] * W] : T(0);
-    reg_l_fwd<T, VBARMS_MAX_BLOCK>(m, dlu + dlu_off[i], x);
+    reg_l_fwd<T, T, VBARMS_MAX_BLOCK>(m, dlu + dlu_off[i], x);
     T *o = out + vp[I] + c;
 #pragma unroll
     for (int r = 0; r < VBARMS_MAX_BLOCK; ++r)
@@ -850,7 +835,8 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
     const int nis = L.nis, nrest = L.nrest;
 
     // Step 4: pivot blocks
-    DBuf<int> dperm(std::max(L.n_is, 1));  // row exchanges of every pivot block as a permutation
+    L.dperm.alloc(std::max(L.n_is, 1));  // row exchanges of every pivot block as a permutation
+    const DBuf<int> &dperm = L.dperm;
     L.dlu_off.alloc(nis + 1);
     {
         DBuf<int64_t> sq(std::max(nis, 1));

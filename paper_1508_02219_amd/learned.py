@@ -233,8 +233,10 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     ap.add_argument("--count", type=int, default=100)
     ap.add_argument("--first-seed", type=int, default=0)
+    ap.add_argument("--sides", type=int, nargs=2, default=SIDES, metavar=("MIN", "MAX"),
+                    help="range of grid sides (nodes per direction) of the matrices")
     a = ap.parse_args(argv)
-    build_dataset(a.count, a.out, first_seed=a.first_seed)
+    build_dataset(a.count, a.out, side_range=tuple(a.sides), first_seed=a.first_seed)
     return 0
 
 

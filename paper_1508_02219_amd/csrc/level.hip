@@ -128,34 +128,94 @@ __global__ void k_block_sq(int nis, const int *is_list, const int *rb, int64_t *
     sq[i] = (int64_t)m * m;
 }
 
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Pivot-block GEPP, one wavefront per block of the independent set (four per workgroup),
+// the block staged in LDS.  The pivot search is a wavefront reduction that picks the row
+// the sequential scan of dev_gepp picks (the first row of largest modulus, the diagonal
+// kept on ties; a NaN never wins and a NaN diagonal keeps its row), and every element
+// update is dev_gepp's, so the factors are the same bit for bit.
 template <class T>
-__global__ void k_gepp(int nis, const int *is_list, const int *rb, const int64_t *rp, const int *ci, const int *co,
-                       const int64_t *wp, const int64_t *vp, const T *v, const int64_t *dlu_off, const int *is_rb,
-                       T *dlu, int *dpiv, int *dperm, double min_ratio, int lvl, int *err) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nis) return;
-    int I = is_list[i];
-    int m = rb[I + 1] - rb[I];
-    int64_t W = wp[I + 1] - wp[I];
-    int64_t k = dev_find(ci, rp[I], rp[I + 1], I);
-    if (k < 0) { dev_set_error(err, VBARMS_ERR_HIP, 2001, I); return; }
-    T *d = dlu + dlu_off[i];
-    const T *a = v + vp[I] + co[k];
-    for (int r = 0; r < m; ++r)
-        for (int c = 0; c < m; ++c) d[r * m + c] = a[r * W + c];
-    if (!dev_gepp(m, d, dpiv + is_rb[i])) {
-        dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, I);
+__global__ void __launch_bounds__(256) k_gepp(int nis, const int *is_list, const int *rb, const int64_t *rp,
+                                              const int *ci, const int *co, const int64_t *wp, const int64_t *vp,
+                                              const T *v, const int64_t *dlu_off, const int *is_rb, T *dlu,
+                                              int *dpiv, int *dperm, double min_ratio, int lvl, int *err) {
+    __shared__ T sa[4][VBARMS_MAX_BLOCK * VBARMS_MAX_BLOCK];
+    __shared__ int spiv[4][VBARMS_MAX_BLOCK];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + w;
+    if (i >= nis) return;  // the whole wavefront leaves; nothing below syncs the workgroup
+    const int I = is_list[i];
+    const int m = rb[I + 1] - rb[I];
+    const int64_t W = wp[I + 1] - wp[I];
+    const int64_t k0 = dev_find(ci, rp[I], rp[I + 1], I);
+    if (k0 < 0) {
+        if (lane == 0) dev_set_error(err, VBARMS_ERR_HIP, 2001, I);
         return;
     }
-    dev_count_illcond<T>(m, d, min_ratio, err);
-    // the row exchanges as one permutation: row r of P x is row dperm[r] of x
-    int *pm = dperm + is_rb[i];
-    const int *pv = dpiv + is_rb[i];
-    for (int r = 0; r < m; ++r) pm[r] = r;
-    for (int r = 0; r < m; ++r) {
-        const int t = pm[r];
-        pm[r] = pm[pv[r]];
-        pm[pv[r]] = t;
+    T *a = sa[w];
+    int *pv = spiv[w];
+    const T *src = v + vp[I] + co[k0];
+    for (int e = lane; e < m * m; e += 64) a[e] = src[(int64_t)(e / m) * W + (e % m)];
+    wave_sync();
+    for (int k = 0; k < m; ++k) {
+        const T akk = fabs(a[k * m + k]);
+        // largest modulus below the diagonal, the first row on ties (NaN as -1)
+        T vv = T(-1);
+        int rr = m;
+        if (lane > k && lane < m) {
+            const T x = fabs(a[lane * m + k]);
+            vv = x != x ? T(-1) : x;
+            rr = lane;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const T ov = __shfl_xor(vv, off, 64);
+            const int orr = __shfl_xor(rr, off, 64);
+            if (ov > vv || (ov == vv && orr < rr)) {
+                vv = ov;
+                rr = orr;
+            }
+        }
+        const int pr = (akk == akk && vv > akk) ? rr : k;
+        const T amax = pr == k ? akk : vv;
+        if (lane == 0) pv[k] = pr;
+        if (amax == T(0)) {
+            if (lane == 0) dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, I);
+            return;
+        }
+        if (pr != k && lane < m) {
+            const T t = a[k * m + lane];
+            a[k * m + lane] = a[pr * m + lane];
+            a[pr * m + lane] = t;
+        }
+        wave_sync();
+        if (lane > k && lane < m) a[lane * m + k] = a[lane * m + k] / a[k * m + k];
+        wave_sync();
+        const int rest = m - k - 1;
+        for (int e = lane; e < rest * rest; e += 64) {
+            const int r = k + 1 + e / rest, c = k + 1 + e % rest;
+            a[r * m + c] = a[r * m + c] - a[r * m + k] * a[k * m + c];
+        }
+        wave_sync();
+    }
+    T *d = dlu + dlu_off[i];
+    for (int e = lane; e < m * m; e += 64) d[e] = a[e];
+    if (lane < m) dpiv[is_rb[i] + lane] = pv[lane];
+    if (lane == 0) {
+        dev_count_illcond<T>(m, a, min_ratio, err);
+        // the row exchanges as one permutation: row r of P x is row dperm[r] of x
+        int *pm = dperm + is_rb[i];
+        for (int r = 0; r < m; ++r) pm[r] = r;
+        for (int r = 0; r < m; ++r) {
+            const int t = pm[r];
+            pm[r] = pm[pv[r]];
+            pm[pv[r]] = t;
+        }
     }
 }
 
@@ -848,7 +908,7 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
         L.dlu.alloc(std::max<int64_t>(tot, 1));
         L.dpiv.alloc(std::max(L.n_is, 1));
         if (nis > 0) {
-            k_gepp<T><<<grid_for(nis, 64), 64, 0, s>>>(nis, L.is_list.p, As.rb.p, As.rp.p, As.ci.p, As.co.p, As.wp.p,
+            k_gepp<T><<<grid_for(nis, 4), 256, 0, s>>>(nis, L.is_list.p, As.rb.p, As.rp.p, As.ci.p, As.co.p, As.wp.p,
                                                       As.vp.p, As.v.p, L.dlu_off.p, L.is_rb.p, L.dlu.p, L.dpiv.p, dperm.p,
                                                       min_ratio, lvl,
                                                       err);

@@ -140,6 +140,9 @@ struct DevCacheStats {
     int64_t runtime_allocs;  // calls that reached hipMalloc
 };
 DevCacheStats dev_cache_stats();
+// Pinned host staging memory of at least `bytes`, owned by the calling host thread and kept
+// (grown, never shrunk) until the process ends; valid until the thread's next call.
+void *pinned_staging(size_t bytes);
 
 template <class T>
 struct DBuf {

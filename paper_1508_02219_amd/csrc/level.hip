@@ -526,8 +526,8 @@ __global__ void k_sym_adj(int p, const int64_t *rp, const int *ci, const int64_t
     if (pass == 0) cnt[v] = c;
 }
 
-HostGroups host_groups(int p, const std::vector<int64_t> &ap, const std::vector<int> &adj, const std::vector<int> &rb,
-                       int gmax, const std::vector<double> *wts) {
+HostGroups host_groups(int p, const int64_t *ap, const int *adj, const std::vector<int> &rb, int gmax,
+                       const std::vector<double> *wts) {
     std::vector<int> order(p);
     for (int I = 0; I < p; ++I) order[I] = I;
     if (wts) std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return (*wts)[a] > (*wts)[b]; });
@@ -573,6 +573,43 @@ HostGroups host_groups(int p, const std::vector<int64_t> &ap, const std::vector<
     return G;
 }
 
+// Neighbour lists of the quotient graph of the pattern of P (A + A^T), built on the device
+// and copied to pinned host memory; `ready` is recorded after the copies (the caller waits
+// on it).  hap[p+1] and hadj[...] stay valid until the thread's next pinned_staging call.
+template <class T>
+void sym_adjacency_to_host(const Panel<T> &P, hipStream_t s, hipEvent_t ready, const int64_t *&hap,
+                           const int *&hadj) {
+    const int p = P.p;
+    DBuf<int> tcnt(std::max(p, 1)), tfill(std::max(p, 1));
+    DBuf<int64_t> tptr(p + 1), acnt(std::max(p, 1)), aptr(p + 1);
+    fill_i32(tcnt.p, 0, p, s);
+    fill_i32(tfill.p, 0, p, s);
+    if (p > 0) {
+        k_tcount<<<grid_for(p, 256), 256, 0, s>>>(p, P.rp.p, P.ci.p, tcnt.p);
+        VB_LAUNCH_CHECK();
+    }
+    const int64_t nt = scan_i32_to_i64(tcnt.p, tptr.p, p, s);
+    DBuf<int> tlist(std::max<int64_t>(nt, 1));
+    if (p > 0) {
+        k_tfill<<<grid_for(p, 256), 256, 0, s>>>(p, P.rp.p, P.ci.p, tptr.p, tfill.p, tlist.p);
+        VB_LAUNCH_CHECK();
+        k_sym_adj<<<grid_for(p, 128), 128, 0, s>>>(p, P.rp.p, P.ci.p, tptr.p, tlist.p, 0, acnt.p, nullptr, nullptr);
+        VB_LAUNCH_CHECK();
+    }
+    const int64_t na = scan_i64(acnt.p, aptr.p, p, s);
+    DBuf<int> adj(std::max<int64_t>(na, 1));
+    if (p > 0) {
+        k_sym_adj<<<grid_for(p, 128), 128, 0, s>>>(p, P.rp.p, P.ci.p, tptr.p, tlist.p, 1, nullptr, aptr.p, adj.p);
+        VB_LAUNCH_CHECK();
+    }
+    char *stage = (char *)pinned_staging(sizeof(int64_t) * (p + 1) + sizeof(int) * (na + 1));
+    hap = (const int64_t *)stage;
+    hadj = (const int *)(stage + sizeof(int64_t) * (p + 1));
+    VB_HIP(hipMemcpyAsync((void *)hap, aptr.p, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToHost, s));
+    if (na) VB_HIP(hipMemcpyAsync((void *)hadj, adj.p, sizeof(int) * na, hipMemcpyDeviceToHost, s));
+    VB_HIP(hipEventRecord(ready, s));
+}
+
 // Upper bound of the distinct coarse block columns of every coarse block row.
 __global__ void k_rg_bound(int pc, const int *mptr, const int *mem, const int64_t *rp, int64_t *cnt) {
     int X = blockIdx.x * blockDim.x + threadIdx.x;
@@ -612,20 +649,20 @@ __global__ void k_rg_crow(int p, const int *rb, const int *cblk, const int *coff
     for (int r = 0; r < rb[I + 1] - rb[I]; ++r) crow[base + r] = rb[I] + r;
 }
 // Coarse panel column of every panel column of the level matrix: block (I, J) lands in
-// coarse block (cblk[I], cblk[J]) at column offset coff[J].  One thread per block row.
-__global__ void k_rg_cols_map(int p, const int *rb, const int64_t *rp, const int *ci, const int *co, const int64_t *wp,
-                              const int *cblk, const int *coff, const int64_t *crp, const int *cci, const int *cco,
-                              int *dstpc, int *err) {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= p) return;
+// coarse block (cblk[I], cblk[J]) at column offset coff[J].  One thread per block.
+__global__ void k_rg_cols_map(int p, int64_t nb, const int *rb, const int64_t *rp, const int *ci, const int *co,
+                              const int64_t *wp, const int *cblk, const int *coff, const int64_t *crp, const int *cci,
+                              const int *cco, int *dstpc, int *err) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nb) return;
+    const int I = (int)dev_floor(rp, 0, p + 1, k);
     const int X = cblk[I];
-    for (int64_t k = rp[I]; k < rp[I + 1]; ++k) {
-        const int J = ci[k];
-        const int64_t pos = dev_find(cci, crp[X], crp[X + 1], cblk[J]);
-        if (pos < 0) { dev_set_error(err, VBARMS_ERR_HIP, 2010, I); return; }
-        const int dc = cco[pos] + coff[J];
-        for (int c = 0; c < rb[J + 1] - rb[J]; ++c) dstpc[wp[I] + co[k] + c] = dc + c;
-    }
+    const int J = ci[k];
+    const int64_t pos = dev_find(cci, crp[X], crp[X + 1], cblk[J]);
+    if (pos < 0) { dev_set_error(err, VBARMS_ERR_HIP, 2010, I); return; }
+    const int dc = cco[pos] + coff[J];
+    int *d = dstpc + wp[I] + co[k];
+    for (int c = 0; c < rb[J + 1] - rb[J]; ++c) d[c] = dc + c;
 }
 // Scatter of the level matrix into the coarse panel (zeroed beforehand): 16 lanes per level
 // row stream its panel row; row r of block I is row coff[I] + r of coarse block cblk[I].
@@ -725,9 +762,11 @@ void regroup_panel(const Panel<T> &A, const HostGroups &G, Panel<T> &Ac, DBuf<in
     }
     if (p > 0) {
         DBuf<int> dstpc(std::max<int64_t>(A.nw, 1));
-        k_rg_cols_map<<<grid_for(p, 128), 128, 0, s>>>(p, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, d_cblk.p, d_coff.p,
-                                                        Ac.rp.p, Ac.ci.p, Ac.co.p, dstpc.p, err);
-        VB_LAUNCH_CHECK();
+        if (A.nb > 0) {
+            k_rg_cols_map<<<grid_for(A.nb, 256), 256, 0, s>>>(p, A.nb, A.rb.p, A.rp.p, A.ci.p, A.co.p, A.wp.p, d_cblk.p,
+                                                               d_coff.p, Ac.rp.p, Ac.ci.p, Ac.co.p, dstpc.p, err);
+            VB_LAUNCH_CHECK();
+        }
         k_rg_vals<T><<<grid_for((int64_t)n * 16, 256), 256, 0, s>>>(n, A.rowblk.p, A.rb.p, A.wp.p, A.vp.p, A.v.p,
                                                                      d_cblk.p, d_coff.p, dstpc.p, Ac.wp.p, Ac.vp.p,
                                                                      Ac.v.p);
@@ -746,6 +785,21 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
     L.n = A.h_rb.empty() ? 0 : A.h_rb.back();
     const int p = L.p, n = L.n;
     if (A.maxm > VBARMS_MAX_BLOCK) fail(VBARMS_ERR_OOM, "block larger than VBARMS_MAX_BLOCK");
+
+    // Step 3 with groups in natural order needs only the pattern: its neighbour lists go to
+    // the host first, so that the host greedy below runs while the device scales
+    const bool grouped = group_rows > 0;
+    const bool early_adjacency = grouped && is_order != 1;
+    const int64_t *hap = nullptr;
+    const int *hadj = nullptr;
+    struct Event {
+        hipEvent_t e = nullptr;
+        ~Event() {
+            if (e) (void)hipEventDestroy(e);
+        }
+    } adj_ready;
+    if (grouped) VB_HIP(hipEventCreateWithFlags(&adj_ready.e, hipEventDisableTiming));
+    if (early_adjacency) sym_adjacency_to_host(L.A, s, adj_ready.e, hap, hadj);
 
     // Step 2: scaling
     L.s1.alloc(std::max(n, 1));
@@ -768,7 +822,6 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
     // Step 3: block independent set on the quotient graph of A + A^T, in natural order or
     // by descending weight; either one supernode per group (parallel LFMIS rounds) or
     // groups of several supernodes merged into one block of a coarse copy of the matrix
-    const bool grouped = group_rows > 0;
     Panel<T> Ac;       // grouped: the level matrix with every group as one block
     DBuf<int> crow;    // grouped: level row of every row of Ac
     HostGroups G;
@@ -783,39 +836,9 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
             VB_LAUNCH_CHECK();
         }
         if (grouped) {
-            // the quotient graph's neighbour lists are built on the device; the host receives
-            // p + 1 offsets and about nb neighbours
-            std::vector<int64_t> hap;
-            std::vector<int> hadj;
             std::vector<double> hw;
-            {
-                DBuf<int> tcnt(std::max(p, 1)), tfill(std::max(p, 1));
-                DBuf<int64_t> tptr(p + 1), acnt(std::max(p, 1)), aptr(p + 1);
-                fill_i32(tcnt.p, 0, p, s);
-                fill_i32(tfill.p, 0, p, s);
-                if (p > 0) {
-                    k_tcount<<<grid_for(p, 256), 256, 0, s>>>(p, As.rp.p, As.ci.p, tcnt.p);
-                    VB_LAUNCH_CHECK();
-                }
-                const int64_t nt = scan_i32_to_i64(tcnt.p, tptr.p, p, s);
-                DBuf<int> tlist(std::max<int64_t>(nt, 1));
-                if (p > 0) {
-                    k_tfill<<<grid_for(p, 256), 256, 0, s>>>(p, As.rp.p, As.ci.p, tptr.p, tfill.p, tlist.p);
-                    VB_LAUNCH_CHECK();
-                    k_sym_adj<<<grid_for(p, 128), 128, 0, s>>>(p, As.rp.p, As.ci.p, tptr.p, tlist.p, 0, acnt.p,
-                                                                nullptr, nullptr);
-                    VB_LAUNCH_CHECK();
-                }
-                const int64_t na = scan_i64(acnt.p, aptr.p, p, s);
-                DBuf<int> adj(std::max<int64_t>(na, 1));
-                if (p > 0) {
-                    k_sym_adj<<<grid_for(p, 128), 128, 0, s>>>(p, As.rp.p, As.ci.p, tptr.p, tlist.p, 1, nullptr,
-                                                                aptr.p, adj.p);
-                    VB_LAUNCH_CHECK();
-                }
-                to_host(hap, aptr.p, p + 1, s);
-                to_host(hadj, adj.p, na, s);
-            }
+            if (!early_adjacency) sym_adjacency_to_host(As, s, adj_ready.e, hap, hadj);
+            VB_HIP(hipEventSynchronize(adj_ready.e));
             if (is_order == 1) to_host(hw, wts.p, p, s);
             G = host_groups(p, hap, hadj, As.h_rb, group_rows, is_order == 1 ? &hw : nullptr);
             regroup_panel(As, G, Ac, crow, err, s);

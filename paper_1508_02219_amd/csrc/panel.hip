@@ -21,15 +21,15 @@ __global__ void k_row_layout(int p, const int *rb, const int *cb, const int64_t 
     area[I] = (int64_t)acc * (rb[I + 1] - rb[I]);
 }
 
-// scalar column list of every panel
-__global__ void k_row_sc(int p, const int *cb, const int64_t *rp, const int *ci, const int64_t *wp, int *sc) {
-    int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= p) return;
-    int64_t w = wp[I];
-    for (int64_t k = rp[I]; k < rp[I + 1]; ++k) {
-        int J = ci[k];
-        for (int c = cb[J]; c < cb[J + 1]; ++c) sc[w++] = c;
-    }
+// scalar column list of every panel, one thread per block
+__global__ void k_row_sc(int p, int64_t nb, const int *cb, const int64_t *rp, const int *ci, const int *co,
+                         const int64_t *wp, int *sc) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nb) return;
+    const int I = (int)dev_floor(rp, 0, p + 1, k);
+    const int J = ci[k];
+    int *d = sc + wp[I] + co[k];
+    for (int c = cb[J]; c < cb[J + 1]; ++c) *d++ = c;
 }
 
 // ---- CSR -> panel ----------------------------------------------------------------
@@ -232,8 +232,8 @@ void panel_finish_layout(Panel<T> &a, hipStream_t s) {
     a.nw = scan_i64(width.p, a.wp.p, a.p, s);
     a.nv = scan_i64(area.p, a.vp.p, a.p, s);
     a.sc.alloc(std::max<int64_t>(a.nw, 1));
-    if (a.p > 0) {
-        k_row_sc<<<grid_for(a.p, 256), 256, 0, s>>>(a.p, a.cb.p, a.rp.p, a.ci.p, a.wp.p, a.sc.p);
+    if (a.nb > 0) {
+        k_row_sc<<<grid_for(a.nb, 256), 256, 0, s>>>(a.p, a.nb, a.cb.p, a.rp.p, a.ci.p, a.co.p, a.wp.p, a.sc.p);
         VB_LAUNCH_CHECK();
     }
 }

@@ -99,6 +99,29 @@ void dev_free(void *p, hipStream_t s) {
     c.cached_bytes += b;
 }
 
+void *pinned_staging(size_t bytes) {
+    struct Staging {
+        void *p = nullptr;
+        size_t n = 0;
+    };
+    // one buffer per host thread; it is not freed at thread exit, since the runtime may be
+    // torn down before thread-local destructors run
+    static thread_local Staging st;
+    if (bytes > st.n) {
+        if (st.p) (void)hipHostFree(st.p);
+        st.p = nullptr;
+        st.n = 0;
+        const size_t want = std::max(bytes + bytes / 2, (size_t)1 << 20);
+        if (hipHostMalloc(&st.p, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            st.p = nullptr;
+            fail(VBARMS_ERR_OOM, "pinned host allocation of " + std::to_string(want) + " bytes failed");
+        }
+        st.n = want;
+    }
+    return st.p;
+}
+
 DevCacheStats dev_cache_stats() {
     DevCache &c = dev_cache();
     std::lock_guard<std::mutex> lk(c.mu);

@@ -35,11 +35,11 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _run_both(vb, orc, s, tau, levels, droptol, drop_schur=1, precision=0, is_order=0):
+def _run_both(vb, orc, s, tau, levels, droptol, drop_schur=1, precision=0, is_order=0, group_rows=0):
     _say(f"[case] {s.name} n={s.n} nnz={s.nnz} tau={tau} levels={levels} t={droptol} is_order={is_order} "
-         f"precision={precision}")
+         f"precision={precision} group_rows={group_rows}")
     perm_o, bptr_o = orc.compress(s.n, s.rowptr, s.col, tau)
-    o = orc.Oracle(s.n, s.rowptr, s.col, s.val, perm_o, bptr_o, levels, droptol, drop_schur, is_order)
+    o = orc.Oracle(s.n, s.rowptr, s.col, s.val, perm_o, bptr_o, levels, droptol, drop_schur, is_order, group_rows)
     sv = vb.Solver()
     rp, ci, va = vb.csr_to_device(s)
     perm, bptr, st = sv.compress(rp, ci, va, tau)
@@ -47,7 +47,7 @@ def _run_both(vb, orc, s, tau, levels, droptol, drop_schur=1, precision=0, is_or
     np.testing.assert_array_equal(bptr.cpu().numpy(), bptr_o)
     err = None
     try:
-        sv.factor(levels, droptol, drop_schur, precision, is_order)
+        sv.factor(levels, droptol, drop_schur, precision, is_order, group_rows)
     except vb.VbarmsError as e:
         err = e
     return o, sv, (rp, ci, va), st, err
@@ -120,17 +120,20 @@ def test_weighted_independent_sets_match_oracle(vb, orc, name, levels):
 
 MIDSIZE = {
     # the 40^3 benchmark recipe at 16^3 (n = 20,480) and the 74^3 variable-block recipe at
-    # 20^3 (n = 31,847): several thousand last-level rows, the benchmark's parameters
-    "grid14_16cubed": lambda: (synth.config_system(2, 0.4), 0.8, 3, 1e-4),
-    "upwind_20cubed": lambda: (synth.config_system(3, 20 / 74), 1.0, 4, 1e-4),
+    # 20^3 (n = 31,847): several thousand last-level rows, the benchmark's parameters (with
+    # its groups, and with one supernode per group)
+    "grid14_16cubed": lambda: (synth.config_system(2, 0.4), 0.8, 3, 1e-4, 0),
+    "grid14_16cubed_groups16": lambda: (synth.config_system(2, 0.4), 0.8, 3, 1e-4, 16),
+    "upwind_20cubed": lambda: (synth.config_system(3, 20 / 74), 1.0, 4, 1e-4, 0),
+    "upwind_20cubed_groups32": lambda: (synth.config_system(3, 20 / 74), 1.0, 4, 1e-4, 32),
 }
 
 
 @pytest.mark.parametrize("name", sorted(MIDSIZE))
 def test_midsize_benchmark_recipes_match_oracle(vb, orc, name):
     import torch
-    s, tau, levels, t = MIDSIZE[name]()
-    o, sv, A, st, err = _run_both(vb, orc, s, tau, levels, t)
+    s, tau, levels, t, groups = MIDSIZE[name]()
+    o, sv, A, st, err = _run_both(vb, orc, s, tau, levels, t, group_rows=groups)
     assert err is None and o.status == 0, err
     _check_all_factors(vb, orc, o, sv)
     x = np.random.default_rng(11).standard_normal(s.n)

@@ -1,11 +1,11 @@
 // Last-level block ILUT (Sec. 3, Alg. 3, IKJ order) and its block triangular solves.
 //
 // Factorization in dependency waves.  Every block row keeps its working row (block list,
-// per-block state and dense blocks) in HBM.  One launch processes all unfinished rows: a
-// row eliminates, in ascending column order exactly like the sequential IKJ loop, every
-// block left of its diagonal whose row was finished in an EARLIER launch; when the next
-// block to eliminate belongs to a row that is not finished yet, the row stops and
-// resumes in the next launch.  Data of other rows is only read across a kernel boundary,
+// per-block state and dense blocks) in HBM.  One launch processes the ready rows: a row
+// eliminates, in ascending column order exactly like the sequential IKJ loop, every block
+// left of its diagonal whose row was finished in an EARLIER launch; when the next block to
+// eliminate belongs to a row that is not finished yet, the row stops and waits for that
+// row and its next few pending columns, and resumes in a later launch.  Data of other rows is only read across a kernel boundary,
 // so no wait, flag protocol or fence is needed inside a kernel.  The smallest unfinished
 // row can never stop, so every launch finishes at least one row.  Finished rows append
 // their L and U blocks to pools, compacted into panels at the end.
@@ -70,6 +70,38 @@ struct IlutRowRec {
 struct RowState {
     int nb, used, last_k, status;  // status: 0 not started, 1 started, 2 finished
 };
+// Waiting-list entry: a row and the rows it awaits (-1: none).  A row that stops at an
+// unfinished row k awaits k and its next pending columns, up to kWaitCols in ascending
+// order, so that it runs again only once it can take that many steps; a row that stopped
+// at the step cap awaits k alone.  Longer lists cut the visits further but defer rows
+// until their backlog exceeds the step cap, which lengthens the chain of launches: of 1,
+// 3, 7 and 15 columns, 3 took the least time on a 74^3-node upwind matrix.
+#ifndef VB_ILUT_WAITCOLS
+#define VB_ILUT_WAITCOLS 3
+#endif
+constexpr int kWaitCols = VB_ILUT_WAITCOLS;
+struct __align__(16) IlutWait {
+    int row;
+    int k[kWaitCols];
+};
+static_assert(sizeof(IlutWait) % 16 == 0, "whole 16-byte words");
+static_assert(kWaitCols >= 2, "k and at least one more column");
+// a <- the N smallest of the ascending list a and the list b, whose columns are distinct
+// from a's (INT_MAX: none); insertion with fixed indices, so both stay in registers
+template <int N>
+__device__ inline void wait_merge(int *a, const int *b) {
+#pragma unroll
+    for (int qb = 0; qb < N; ++qb) {
+        int x = b[qb];
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            if (x < a[q]) {
+                const int tmp = a[q];
+                a[q] = x;
+                x = tmp;
+            }
+    }
+}
 
 // open-addressing hash in LDS (capacity hmask + 1, a power of two, at least 1.5 times the
 // number of keys, so a probe always ends at a free slot)
@@ -91,14 +123,11 @@ __device__ inline void h_insert(int *keys, int *vals, unsigned hmask, int key, i
     }
 }
 
-// Multiplier solve e <- e U^{-1} L^{-1} P for a pivot block of size MK held in LDS: the
-// same operations in the same order as the generic row solves, with the row kept in
-// registers so that only the (independent) loads of the LU factors remain in LDS.
+// Multiplier solve x <- x U^{-1} L^{-1} P for a row x in registers and a pivot block of
+// size MK held in LDS: the same operations in the same order as the generic row solves,
+// so that only the (independent) loads of the LU factors remain in LDS.
 template <class T, int MK>
-__device__ inline void mult_solve_reg(const T *lu, const int *piv, T *e) {
-    T x[MK];
-#pragma unroll
-    for (int c = 0; c < MK; ++c) x[c] = e[c];
+__device__ inline void mult_solve_reg(const T *lu, const int *piv, T *x) {
 #pragma unroll
     for (int c = 0; c < MK; ++c) {
         T s = x[c];
@@ -125,21 +154,6 @@ __device__ inline void mult_solve_reg(const T *lu, const int *piv, T *e) {
         for (int j = 0; j < MK; ++j) x[j] = j == pk ? xk : x[j];
         x[k] = xp;
     }
-#pragma unroll
-    for (int c = 0; c < MK; ++c) e[c] = x[c];
-}
-template <class T>
-__device__ inline void mult_solve(int mk, const T *lu, const int *piv, T *e) {
-    switch (mk) {
-        case 1: mult_solve_reg<T, 1>(lu, piv, e); return;
-        case 2: mult_solve_reg<T, 2>(lu, piv, e); return;
-        case 3: mult_solve_reg<T, 3>(lu, piv, e); return;
-        case 4: mult_solve_reg<T, 4>(lu, piv, e); return;
-        case 5: mult_solve_reg<T, 5>(lu, piv, e); return;
-        default:
-            dev_row_solve_u<T>(mk, lu, e, 1);
-            dev_row_solve_lp<T>(mk, lu, piv, e, 1);
-    }
 }
 // drop rule ||B||_F / (m n) < t for a contiguous row-major block: the squares are summed in
 // index order like the generic test, with the loads issued four at a time
@@ -163,6 +177,57 @@ __device__ inline bool drop_contig(int m, int n, const T *b, double t) {
     return s < thr * thr;
 }
 
+// The m x mk multiplier block M (row-major in LDS) <- M U^{-1} L^{-1} P, one lane of the
+// calling wavefront per row, followed by the drop rule ||M||_F / (m mk) < t.  The squares
+// are summed in index order, one row after the other: each lane continues the running sum
+// of the previous row's lane from its registers.  Returns the drop decision to every lane.
+// Pivot blocks above 5 x 5 are solved in LDS (unrolled register solves of that size would
+// cost the kernel a resident wavefront per SIMD).
+template <class T, int MK>
+__device__ inline bool mult_solve_drop_reg(int m, const T *lu, const int *piv, T *M, double t) {
+    const int lane = threadIdx.x & 63;
+    T x[MK];
+#pragma unroll
+    for (int c = 0; c < MK; ++c) x[c] = T(0);
+    if (lane < m) {
+        T *e = M + lane * MK;
+#pragma unroll
+        for (int c = 0; c < MK; ++c) x[c] = e[c];
+        mult_solve_reg<T, MK>(lu, piv, x);
+#pragma unroll
+        for (int c = 0; c < MK; ++c) e[c] = x[c];
+    }
+    T s = T(0);
+    for (int r = 0; r < m; ++r) {
+        if (lane == r)
+#pragma unroll
+            for (int c = 0; c < MK; ++c) s = s + x[c] * x[c];
+        s = __shfl(s, r, 64);
+    }
+    const T thr = T(t) * T(m * MK);
+    return s < thr * thr;
+}
+template <class T>
+__device__ inline bool mult_solve_drop(int m, int mk, const T *lu, const int *piv, T *M, double t) {
+    switch (mk) {
+        case 1: return mult_solve_drop_reg<T, 1>(m, lu, piv, M, t);
+        case 2: return mult_solve_drop_reg<T, 2>(m, lu, piv, M, t);
+        case 3: return mult_solve_drop_reg<T, 3>(m, lu, piv, M, t);
+        case 4: return mult_solve_drop_reg<T, 4>(m, lu, piv, M, t);
+        case 5: return mult_solve_drop_reg<T, 5>(m, lu, piv, M, t);
+        default: {
+            const int lane = threadIdx.x & 63;
+            if (lane < m) {
+                dev_row_solve_u<T>(mk, lu, M + lane * mk, 1);
+                dev_row_solve_lp<T>(mk, lu, piv, M + lane * mk, 1);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            return drop_contig<T>(m, mk, M, t);
+        }
+    }
+}
 // Copies a rows x tw tile (row stride ld in global memory) to LDS (row stride tw).  Each
 // thread issues up to four loads before it stores any, so the loads are in flight together.
 template <class T>
@@ -195,11 +260,12 @@ __device__ inline void stage_tile(T *dst, const T *src, int64_t ld, int rows, in
 // small dense solves, which keep the operation order of the sequential algorithm.  A row
 // that meets an unfinished row k saves its list and appends itself to the output list.
 //
-// A row that meets an unfinished row k records k and appends itself to the waiting list;
-// the gather kernel of a later launch returns it to the ready list once k has finished.
+// A row that meets an unfinished row k records k, with its next pending columns, and
+// appends itself to the waiting list; the gather kernel of a later launch returns it to the
+// ready list once all of them have finished.
 template <class T>
 __device__ void ilut_row(
-    const int i, int launch, int min_ready, int p, int2 *wait_out, int *cnt_wait_out, int *nfinished,
+    const int i, int launch, int min_ready, int p, IlutWait *wait_out, int *cnt_wait_out, int *nfinished,
     const int *rb, const int64_t *rp, const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av,
     double droptol, double min_ratio, int *done, RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols,
     int *woffs, unsigned char *west, T *wvals, T *dl, const int64_t *dl_off, int *dl_piv, IlutRowRec *rec, int *lci,
@@ -228,6 +294,8 @@ __device__ void ilut_row(
     const int kRowCap = lds.rbcap;
     __shared__ int s_nb, s_used, s_last, s_status, s_stop, s_nb0;
     __shared__ int s_wmin[kIlutThreads / 64];
+    __shared__ int s_wk[kIlutThreads / 64][kWaitCols - 1];
+    __shared__ int s_drop;
     __shared__ int s_lc, s_lw, s_uc, s_uw;
     __shared__ int64_t s_lb, s_lv, s_ub, s_uv;
     const int t = threadIdx.x;
@@ -393,6 +461,36 @@ __device__ void ilut_row(
         if (capped || !(dk > 0 && dk < launch)) {
             // not usable now: save the state of the list (the columns and offsets of
             // entries loaded at the start of this visit are unchanged)
+            {
+                // the kWaitCols - 1 smallest pending columns after k (none at the step cap):
+                // each thread keeps its smallest in ascending order, each wavefront merges
+                // them, and thread 0 merges the wavefronts after the barrier
+                int c[kWaitCols - 1];
+#pragma unroll
+                for (int q = 0; q < kWaitCols - 1; ++q) c[q] = INT_MAX;
+                if (!capped)
+                    for (int e = t; e < s_nb; e += kIlutThreads) {
+                        int K = l_cols[e];
+                        if (K <= k || K >= i || l_est[e] != 0) continue;
+#pragma unroll
+                        for (int q = 0; q < kWaitCols - 1; ++q)
+                            if (K < c[q]) {
+                                const int tmp = c[q];
+                                c[q] = K;
+                                K = tmp;
+                            }
+                    }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    int o[kWaitCols - 1];
+#pragma unroll
+                    for (int q = 0; q < kWaitCols - 1; ++q) o[q] = __shfl_xor(c[q], off, 64);
+                    wait_merge<kWaitCols - 1>(c, o);
+                }
+                if ((t & 63) == 0)
+#pragma unroll
+                    for (int q = 0; q < kWaitCols - 1; ++q) s_wk[t >> 6][q] = c[q];
+            }
             for (int e = t; e < s_nb; e += kIlutThreads) {
                 if (e >= s_nb0) {
                     cols[e] = l_cols[e];
@@ -400,11 +498,27 @@ __device__ void ilut_row(
                 }
                 est[e] = l_est[e];
             }
+            __syncthreads();
             if (t == 0) {
+                int c[kWaitCols - 1];
+#pragma unroll
+                for (int q = 0; q < kWaitCols - 1; ++q) c[q] = s_wk[0][q];
+                for (int w = 1; w < kIlutThreads / 64; ++w) {
+                    int o[kWaitCols - 1];
+#pragma unroll
+                    for (int q = 0; q < kWaitCols - 1; ++q) o[q] = s_wk[w][q];
+                    wait_merge<kWaitCols - 1>(c, o);
+                }
                 rs[i] = RowState{s_nb, s_used, last, 1};
-                nbytes += 8ull * (s_nb - s_nb0) + s_nb + 24;
-                // wait on row k; everything written here is read in a later launch
-                wait_out[atomicAdd(cnt_wait_out, 1)] = make_int2(i, k);
+                nbytes += 8ull * (s_nb - s_nb0) + s_nb + 16 + sizeof(IlutWait);
+                // wait on row k (and the next pending ones); everything written here is read
+                // in a later launch
+                IlutWait wt;
+                wt.row = i;
+                wt.k[0] = k;
+#pragma unroll
+                for (int q = 0; q < kWaitCols - 1; ++q) wt.k[q + 1] = c[q] == INT_MAX ? -1 : c[q];
+                wait_out[atomicAdd(cnt_wait_out, 1)] = wt;
                 atomicAdd(moved, nbytes);
             }
             return;
@@ -441,10 +555,12 @@ __device__ void ilut_row(
             stage_tile<T>(s_U, uv + rk.uv, UW, mk, UW < TW ? UW : TW, t);
         }
         __syncthreads();
-        if (t < m) mult_solve<T>(mk, s_lu, s_piv, s_M + t * mk);
+        if (t < 64) {
+            const bool d = mult_solve_drop<T>(m, mk, s_lu, s_piv, s_M, droptol);
+            if (t == 0) s_drop = d ? 1 : 0;
+        }
         __syncthreads();
-        // every thread evaluates the drop test on the same LDS block in the same order
-        const bool dropped = drop_contig<T>(m, mk, s_M, droptol);
+        const bool dropped = s_drop != 0;
         if (t == 0) {
             // readiness and record of row k, its pivot block, the multiplier in and out
             nbytes += 68ull + (unsigned long long)S * mk * mk + 4ull * mk + 2ull * S * m * mk;
@@ -650,18 +766,18 @@ __device__ void ilut_row(
     }
 }
 
-// Gather of a launch: waiting rows whose awaited row has finished (in an earlier launch)
-// move to the ready list, the others stay on the waiting list.  A waiting entry is the pair
-// (row, awaited row); rows that never ran await nothing (-1).  Each workgroup takes 1024
-// consecutive entries at a time, four per thread with all loads issued before use, and
-// appends them with one atomic per list (positions from wavefront ballots and an LDS scan
-// over the wavefronts).
+// Gather of a launch: waiting rows whose awaited rows have all finished (in an earlier
+// launch) move to the ready list, the others stay on the waiting list.  Rows that never ran
+// await nothing.  Each workgroup takes 1024 consecutive entries at a time, four per thread
+// with all loads issued before use, and appends them with one atomic per list (positions
+// from wavefront ballots and an LDS scan over the wavefronts).
 constexpr int kGatherThreads = 256;
 constexpr int kGatherItems = 4;
 
-__global__ void __launch_bounds__(kGatherThreads) k_ilut_gather(const int2 *wait_in, const int *cnt_wait_in,
+__global__ void __launch_bounds__(kGatherThreads) k_ilut_gather(const IlutWait *wait_in, const int *cnt_wait_in,
                                                                 const int *done, int *ready, int *cnt_ready,
-                                                                int2 *wait_out, int *cnt_wait_out, int *min_ready) {
+                                                                IlutWait *wait_out, int *cnt_wait_out,
+                                                                int *min_ready) {
     constexpr int NW = kGatherThreads / 64;
     __shared__ int s_tr[NW], s_tw[NW], s_br[NW], s_bw[NW], s_mn[NW];
     const int n = *cnt_wait_in;
@@ -669,28 +785,39 @@ __global__ void __launch_bounds__(kGatherThreads) k_ilut_gather(const int2 *wait
     const unsigned long long lt = (1ull << lane) - 1ull;
     constexpr int tile = kGatherThreads * kGatherItems;
     for (int b0 = blockIdx.x * tile; b0 < n; b0 += gridDim.x * tile) {
-        int2 ent[kGatherItems];
+        IlutWait ent[kGatherItems];
         bool has[kGatherItems], rdy[kGatherItems];
 #pragma unroll
         for (int u = 0; u < kGatherItems; ++u) {
             const int e = b0 + u * kGatherThreads + t;
             has[u] = e < n;
-            ent[u] = has[u] ? wait_in[e] : make_int2(-1, -1);
-        }
-        int dk[kGatherItems];
+            if (has[u]) {
+                ent[u] = wait_in[e];
+            } else {
+                ent[u].row = -1;
 #pragma unroll
-        for (int u = 0; u < kGatherItems; ++u) dk[u] = has[u] && ent[u].y >= 0 ? done[ent[u].y] : 1;
+                for (int q = 0; q < kWaitCols; ++q) ent[u].k[q] = -1;
+            }
+        }
+        int dk[kGatherItems][kWaitCols];
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u)
+#pragma unroll
+            for (int q = 0; q < kWaitCols; ++q) dk[u][q] = ent[u].k[q] >= 0 ? done[ent[u].k[q]] : 1;
         int pr[kGatherItems], pw[kGatherItems];
         int tr = 0, tw = 0, mn = INT_MAX;
 #pragma unroll
         for (int u = 0; u < kGatherItems; ++u) {
-            rdy[u] = has[u] && dk[u] != 0;
+            bool all = true;
+#pragma unroll
+            for (int q = 0; q < kWaitCols; ++q) all = all && dk[u][q] != 0;
+            rdy[u] = has[u] && all;
             const unsigned long long mr = __ballot(rdy[u]), mw = __ballot(has[u] && !rdy[u]);
             pr[u] = tr + __popcll(mr & lt);
             pw[u] = tw + __popcll(mw & lt);
             tr += __popcll(mr);
             tw += __popcll(mw);
-            if (rdy[u] && ent[u].x < mn) mn = ent[u].x;
+            if (rdy[u] && ent[u].row < mn) mn = ent[u].row;
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -724,7 +851,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_ilut_gather(const int2 *wait
 #pragma unroll
         for (int u = 0; u < kGatherItems; ++u) {
             if (!has[u]) continue;
-            if (rdy[u]) ready[s_br[wv] + pr[u]] = ent[u].x;
+            if (rdy[u]) ready[s_br[wv] + pr[u]] = ent[u].row;
             else wait_out[s_bw[wv] + pw[u]] = ent[u];
         }
         __syncthreads();  // s_br / s_bw are rewritten by the next tile
@@ -732,9 +859,15 @@ __global__ void __launch_bounds__(kGatherThreads) k_ilut_gather(const int2 *wait
 }
 
 // waiting list of the first launch: every row, awaiting nothing
-__global__ void k_wait_init(int p, int2 *w) {
+__global__ void k_wait_init(int p, IlutWait *w) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < p) w[i] = make_int2(i, -1);
+    if (i < p) {
+        IlutWait e;
+        e.row = i;
+#pragma unroll
+        for (int q = 0; q < kWaitCols; ++q) e.k[q] = -1;
+        w[i] = e;
+    }
 }
 
 // One launch: a fixed grid strides over the ready list.  Counter slots: the gather of
@@ -744,7 +877,7 @@ __global__ void k_wait_init(int p, int2 *w) {
 template <class T>
 __global__ void __launch_bounds__(kIlutThreads, VB_ILUT_MINWAVES) k_ilut_wave(
     int launch, int p, const int *ready, const int *cnt_ready, int *cnt_ready_clear, const int *min_ready_in,
-    int *min_ready_clear, int2 *wait_out,
+    int *min_ready_clear, IlutWait *wait_out,
     int *cnt_wait_out, int *cnt_wait_clear, int *nfinished, const int *rb, const int64_t *rp,
     const int *ci, const int *co, const int64_t *wp, const int64_t *vp, const T *av, double droptol, double min_ratio,
     int *done, RowState *rs, const int64_t *boff, const int64_t *voff, int *wcols, int *woffs, unsigned char *west,
@@ -1022,7 +1155,7 @@ void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, 
         const size_t lds_bytes = ilut_lds_bytes<T>(lds);
         // cnt: three rotating waiting-list counters, two ready counters, finished rows
         DBuf<int> done(p), ready(p), cnt(8);
-        DBuf<int2> waits(2 * (size_t)p);
+        DBuf<IlutWait> waits(2 * (size_t)p);
         DBuf<unsigned long long> moved(1);
         fill_val<unsigned long long>(moved.p, 0ull, 1, s);
         VB_HIP(hipMemsetAsync(rs.p, 0, sizeof(RowState) * p, s));
@@ -1038,15 +1171,26 @@ void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, 
         int *cw = cnt.p, *cr = cnt.p + 3, *nfin = cnt.p + 5, *mr = cnt.p + 6;
         const unsigned grid = (unsigned)std::min(p, kIlutGrid);
         int finished = 0, launch = 0, code = 0, eblock = 0;
-        while (finished < p) {
-            // every launch finishes at least one row: the smallest unfinished row depends only
-            // on rows finished in earlier launches, so the gather always finds it ready, and as
-            // the smallest ready row it is exempt from the step cap
-            if (launch > p + kCheckEvery) fail(VBARMS_ERR_HIP, "block ILUT made no progress");
+        // Groups of kCheckEvery launches, each followed by a copy of the finished-row count
+        // and the error record into pinned memory and an event.  The host queues group g + 1
+        // before it waits for the record of group g, so the device never idles on the check;
+        // a group queued after the last row finished sees empty lists and does nothing.
+        int *hrec = (int *)pinned_staging(2 * 16 * sizeof(int));
+        hipEvent_t gev[2] = {nullptr, nullptr};
+        VB_HIP(hipEventCreateWithFlags(&gev[0], hipEventDisableTiming));
+        VB_HIP(hipEventCreateWithFlags(&gev[1], hipEventDisableTiming));
+        struct EvGuard {
+            hipEvent_t *e;
+            ~EvGuard() {
+                (void)hipEventDestroy(e[0]);
+                (void)hipEventDestroy(e[1]);
+            }
+        } evg{gev};
+        auto queue_group = [&](int g) {
             for (int q = 0; q < kCheckEvery; ++q) {
                 ++launch;
-                const int2 *w_in = waits.p + (size_t)(launch & 1) * p;
-                int2 *w_out = waits.p + (size_t)((launch + 1) & 1) * p;
+                const IlutWait *w_in = waits.p + (size_t)(launch & 1) * p;
+                IlutWait *w_out = waits.p + (size_t)((launch + 1) & 1) * p;
                 k_ilut_gather<<<kGatherBlocks, kGatherThreads, 0, s>>>(w_in, cw + launch % 3, done.p, ready.p,
                                                             cr + launch % 2, w_out, cw + (launch + 1) % 3,
                                                             mr + launch % 2);
@@ -1061,19 +1205,38 @@ void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, 
                     capv_pool, err, lvl, moved.p, lds);
                 VB_LAUNCH_CHECK();
             }
-            // both records come back with one synchronization
-            std::vector<int> hc(6), herr(4);
-            VB_HIP(hipMemcpyAsync(hc.data(), cnt.p, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
-            VB_HIP(hipMemcpyAsync(herr.data(), err, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-            VB_HIP(hipStreamSynchronize(s));
-            code = herr[0];
-            eblock = herr[2];
+            int *slot = hrec + 16 * (g & 1);
+            VB_HIP(hipMemcpyAsync(slot, cnt.p, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+            VB_HIP(hipMemcpyAsync(slot + 8, err, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+            VB_HIP(hipEventRecord(gev[g & 1], s));
+        };
+        queue_group(0);
+        int waves = 0;
+        for (int g = 0;; ++g) {
+            // every launch finishes at least one row: the smallest unfinished row depends only
+            // on rows finished in earlier launches, so the gather always finds it ready, and as
+            // the smallest ready row it is exempt from the step cap
+            if ((int64_t)g * kCheckEvery > (int64_t)p + kCheckEvery) {
+                (void)hipStreamSynchronize(s);
+                fail(VBARMS_ERR_HIP, "block ILUT made no progress");
+            }
+            queue_group(g + 1);
+            VB_HIP(hipEventSynchronize(gev[g & 1]));
+            const int *slot = hrec + 16 * (g & 1);
+            code = slot[8];
+            eblock = slot[10];
+            waves = (g + 1) * kCheckEvery;
             if (code != 0) break;
-            const int now = hc[5];
-            if (now < p && now < finished + kCheckEvery) fail(VBARMS_ERR_HIP, "block ILUT made no progress");
+            const int now = slot[5];
+            if (now < p && now < finished + kCheckEvery) {
+                (void)hipStreamSynchronize(s);
+                fail(VBARMS_ERR_HIP, "block ILUT made no progress");
+            }
             finished = now;
+            if (finished >= p) break;
         }
-        last.waves = launch;
+        VB_HIP(hipStreamSynchronize(s));  // the group queued after the last check
+        last.waves = waves;
         {
             // the bytes the waves moved, credited to the ILUT timing class
             KTimer *kt = cur_ktimer();

@@ -134,6 +134,8 @@ __device__ inline void mult_solve_reg(const T *lu, const int *piv, T *x) {
 #pragma unroll
         for (int q = 0; q < c; ++q) s = s - x[q] * lu[q * MK + c];
         x[c] = s / lu[c * MK + c];
+        // above 5 x 5, one column's LU loads at a time (bounds the registers in flight)
+        if (MK > 5) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int c = MK - 1; c >= 0; --c) {
@@ -141,6 +143,7 @@ __device__ inline void mult_solve_reg(const T *lu, const int *piv, T *x) {
 #pragma unroll
         for (int q = c + 1; q < MK; ++q) s = s - x[q] * lu[q * MK + c];
         x[c] = s;
+        if (MK > 5) __builtin_amdgcn_sched_barrier(0);
     }
     // row interchanges, last pivot first, as selects over the register array
 #pragma unroll
@@ -181,7 +184,7 @@ __device__ inline bool drop_contig(int m, int n, const T *b, double t) {
 // calling wavefront per row, followed by the drop rule ||M||_F / (m mk) < t.  The squares
 // are summed in index order, one row after the other: each lane continues the running sum
 // of the previous row's lane from its registers.  Returns the drop decision to every lane.
-// Pivot blocks above 5 x 5 are solved in LDS (unrolled register solves of that size would
+// Larger pivot blocks are solved in LDS (unrolled register solves of those sizes would
 // cost the kernel a resident wavefront per SIMD).
 template <class T, int MK>
 __device__ inline bool mult_solve_drop_reg(int m, const T *lu, const int *piv, T *M, double t) {
@@ -215,29 +218,37 @@ __device__ inline bool mult_solve_drop(int m, int mk, const T *lu, const int *pi
         case 3: return mult_solve_drop_reg<T, 3>(m, lu, piv, M, t);
         case 4: return mult_solve_drop_reg<T, 4>(m, lu, piv, M, t);
         case 5: return mult_solve_drop_reg<T, 5>(m, lu, piv, M, t);
-        default: {
-            const int lane = threadIdx.x & 63;
-            if (lane < m) {
-                dev_row_solve_u<T>(mk, lu, M + lane * mk, 1);
-                dev_row_solve_lp<T>(mk, lu, piv, M + lane * mk, 1);
-            }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            return drop_contig<T>(m, mk, M, t);
-        }
+        // in single precision 6 x 6 and 7 x 7 also fit the kernel's register budget
+        case 6:
+            if constexpr (sizeof(T) == 4) return mult_solve_drop_reg<T, 6>(m, lu, piv, M, t);
+            break;
+        case 7:
+            if constexpr (sizeof(T) == 4) return mult_solve_drop_reg<T, 7>(m, lu, piv, M, t);
+            break;
+        default: break;
     }
+    const int lane = threadIdx.x & 63;
+    if (lane < m) {
+        dev_row_solve_u<T>(mk, lu, M + lane * mk, 1);
+        dev_row_solve_lp<T>(mk, lu, piv, M + lane * mk, 1);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return drop_contig<T>(m, mk, M, t);
 }
-// Copies a rows x tw tile (row stride ld in global memory) to LDS (row stride tw).  Each
-// thread issues up to four loads before it stores any, so the loads are in flight together.
+// Copies a rows x tw tile (row stride ld in global memory) to LDS (row stride tw) with nt
+// threads (t = 0..nt-1).  Each thread issues up to six loads before it stores any, so the
+// loads are in flight together.
 template <class T>
-__device__ inline void stage_tile(T *dst, const T *src, int64_t ld, int rows, int tw, int t) {
+__device__ inline void stage_tile(T *dst, const T *src, int64_t ld, int rows, int tw, int t, int nt) {
+    constexpr int kPer = 6;
     const int tot = rows * tw;
-    for (int e0 = 0; e0 < tot; e0 += 4 * kIlutThreads) {
-        T v[4];
+    for (int e0 = 0; e0 < tot; e0 += kPer * nt) {
+        T v[kPer];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = e0 + u * kIlutThreads + t;
+        for (int u = 0; u < kPer; ++u) {
+            const int e = e0 + u * nt + t;
             v[u] = T(0);
             if (e < tot) {
                 const int q = e / tw, cc = e - q * tw;
@@ -245,8 +256,8 @@ __device__ inline void stage_tile(T *dst, const T *src, int64_t ld, int rows, in
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = e0 + u * kIlutThreads + t;
+        for (int u = 0; u < kPer; ++u) {
+            const int e = e0 + u * nt + t;
             if (e < tot) dst[e] = v[u];
         }
     }
@@ -309,8 +320,8 @@ __device__ void ilut_row(
     int *offs = woffs + B0;
     unsigned char *est = west + B0;
     T *w = wvals + V0;
-    // the column map packs a w offset with the block width (6 bits)
-    const bool use_map = CV < ((int64_t)1 << 25);
+    // the column map packs a w offset with a "new block" bit and the block width (6 bits)
+    const bool use_map = CV < ((int64_t)1 << 24);
     // the first kSpecEntries saved list entries are loaded together with the row state (a
     // row's list region holds at least 64 entries; on a first visit they are not used)
     constexpr int kSpecEntries = 64;
@@ -540,22 +551,29 @@ __device__ void ilut_row(
             }
         }
         const int TW = lds.ustage / mk;
-        // stage the pivot-block LU of row k, its pivots, the multiplier block, U row k's
-        // block lists and the first tile of its values; all these loads are independent
-        {
+        // Wavefront 0 stages the pivot-block LU of row k, its pivots and the multiplier block,
+        // and solves and tests the multiplier; meanwhile the other wavefronts stage U row k's
+        // block lists and the first tile of its values.  One barrier joins them.
+        constexpr int kUT = kIlutThreads > 64 ? 64 : 0;  // first thread that stages U row k
+        if (t < 64) {
             const T *dkp = dl + rk.lu0;
-            for (int e = t; e < mk * mk; e += kIlutThreads) s_lu[e] = dkp[e];
-            for (int q = t; q < mk; q += kIlutThreads) s_piv[q] = dl_piv[rk.rbeg + q];
+            for (int e = t; e < mk * mk; e += 64) s_lu[e] = dkp[e];
+            for (int q = t; q < mk; q += 64) s_piv[q] = dl_piv[rk.rbeg + q];
             const T *Mg = w + l_offs[ek];
-            for (int e = t; e < m * mk; e += kIlutThreads) s_M[e] = Mg[e];
-            for (int b = t; b < rk.uc; b += kIlutThreads) {
+            for (int e = t; e < m * mk; e += 64) s_M[e] = Mg[e];
+        }
+        if (t >= kUT) {
+            for (int b = t - kUT; b < rk.uc; b += kIlutThreads - kUT) {
                 s_ucol[b] = uci[rk.ub + b];
                 s_uc0[b] = uco[rk.ub + b];
             }
-            stage_tile<T>(s_U, uv + rk.uv, UW, mk, UW < TW ? UW : TW, t);
+            stage_tile<T>(s_U, uv + rk.uv, UW, mk, UW < TW ? UW : TW, t - kUT, kIlutThreads - kUT);
         }
-        __syncthreads();
         if (t < 64) {
+            // the wavefront's own LDS stores are complete before its solve reads them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
             const bool d = mult_solve_drop<T>(m, mk, s_lu, s_piv, s_M, droptol);
             if (t == 0) s_drop = d ? 1 : 0;
         }
@@ -594,7 +612,7 @@ __device__ void ilut_row(
                 const int off = l_offs[e0];
                 s_uoff[b] = off;
                 if (use_map)
-                    for (int q = 0; q < nJ && s_uc0[b] + q < lds.ustage; ++q) s_cmap[s_uc0[b] + q] = ((off + q) << 6) | nJ;
+                    for (int q = 0; q < nJ && s_uc0[b] + q < lds.ustage; ++q) s_cmap[s_uc0[b] + q] = ((off + q) << 7) | nJ;
                 continue;
             }
             int e = atomicAdd(&s_nb, 1);
@@ -609,12 +627,20 @@ __device__ void ilut_row(
             l_offs[e] = off;
             l_est[e] = 0;
             s_uoff[b] = off;
+            // a new block starts from zero: the update below writes every value of it
+            // without reading w first, so it needs no clearing
+            s_un[b] = nJ | 256;
             if (use_map)
-                for (int q = 0; q < nJ && s_uc0[b] + q < lds.ustage; ++q) s_cmap[s_uc0[b] + q] = ((off + q) << 6) | nJ;
-            for (int q = 0; q < m * nJ; ++q) w[off + q] = T(0);
+                for (int q = 0; q < nJ && s_uc0[b] + q < lds.ustage; ++q)
+                    s_cmap[s_uc0[b] + q] = ((off + q) << 7) | 64 | nJ;
             h_insert(hkeys, hvals, hmask, J, e);
         }
-        __syncthreads();
+        // LDS only: the update reads the block list, the maps and the staged tiles from LDS;
+        // the w blocks it reads were last written before the scan's full barrier, and the
+        // multiplier block stored above is not read again in this step
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
         if (s_stop) {
             if (t == 0) atomicAdd(moved, nbytes);
             return;
@@ -626,7 +652,7 @@ __device__ void ilut_row(
             const int tw = UW - c0 < TW ? UW - c0 : TW;
             if (c0 > 0) {
                 __syncthreads();  // the previous tile is consumed
-                stage_tile<T>(s_U, uv + rk.uv + c0, UW, mk, tw, t);
+                stage_tile<T>(s_U, uv + rk.uv + c0, UW, mk, tw, t, kIlutThreads);
                 __syncthreads();
             }
             // each thread takes up to four (row, column) pairs at a time and loads their w
@@ -637,22 +663,26 @@ __device__ void ilut_row(
                 T *wq[4];
                 T val[4];
                 int rq[4], cq[4];
+                bool fresh[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int e = e0 + u * kIlutThreads + t;
                     wq[u] = nullptr;
                     val[u] = T(0);
                     rq[u] = cq[u] = 0;
+                    fresh[u] = false;
                     if (e < tot) {
                         const int r = e / tw, cc = e - r * tw, c = c0 + cc;
                         int base, nJ;
                         if (use_map && c < lds.ustage) {
                             const int code = s_cmap[c];
-                            base = code >> 6;
+                            base = code >> 7;
+                            fresh[u] = (code & 64) != 0;
                             nJ = code & 63;
                         } else {
                             const int b = (int)dev_floor32(s_uc0, 0, rk.uc, c);
-                            nJ = s_un[b];
+                            nJ = s_un[b] & 255;
+                            fresh[u] = s_un[b] > 255;
                             base = s_uoff[b] + (c - s_uc0[b]);
                         }
                         wq[u] = w + base + r * nJ;
@@ -662,7 +692,7 @@ __device__ void ilut_row(
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    if (wq[u]) val[u] = *wq[u];
+                    if (wq[u] && !fresh[u]) val[u] = *wq[u];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (!wq[u]) continue;

@@ -312,6 +312,63 @@ __device__ inline bool dev_gepp(int m, T *a, int *piv) {
     }
     return true;
 }
+// Barrier of one wavefront: its LDS and memory operations issued so far are visible to
+// its other lanes.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+// dev_gepp by one wavefront (all 64 lanes call it; m <= 64) on the row-major block a in
+// LDS, pivots in pv (LDS).  The pivot search is a wavefront reduction that picks the row
+// the sequential scan picks (the first row of largest modulus, the diagonal kept on ties;
+// a NaN never wins and a NaN diagonal keeps its row), and every element update is
+// dev_gepp's, so the factors are the same bit for bit.  Returns false at a zero pivot
+// (pv[k] written for that column), like dev_gepp.
+template <class T>
+__device__ inline bool wave_gepp(int m, T *a, int *pv, int lane) {
+    for (int k = 0; k < m; ++k) {
+        const T akk = fabs(a[k * m + k]);
+        // largest modulus below the diagonal, the first row on ties (NaN as -1)
+        T vv = T(-1);
+        int rr = m;
+        if (lane > k && lane < m) {
+            const T x = fabs(a[lane * m + k]);
+            vv = x != x ? T(-1) : x;
+            rr = lane;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const T ov = __shfl_xor(vv, off, 64);
+            const int orr = __shfl_xor(rr, off, 64);
+            if (ov > vv || (ov == vv && orr < rr)) {
+                vv = ov;
+                rr = orr;
+            }
+        }
+        const int pr = (akk == akk && vv > akk) ? rr : k;
+        const T amax = pr == k ? akk : vv;
+        if (lane == 0) pv[k] = pr;
+        if (amax == T(0)) {
+            return false;
+        }
+        if (pr != k && lane < m) {
+            const T t = a[k * m + lane];
+            a[k * m + lane] = a[pr * m + lane];
+            a[pr * m + lane] = t;
+        }
+        wave_sync();
+        if (lane > k && lane < m) a[lane * m + k] = a[lane * m + k] / a[k * m + k];
+        wave_sync();
+        const int rest = m - k - 1;
+        for (int e = lane; e < rest * rest; e += 64) {
+            const int r = k + 1 + e / rest, c = k + 1 + e % rest;
+            a[r * m + c] = a[r * m + c] - a[r * m + k] * a[k * m + c];
+        }
+        wave_sync();
+    }
+    return true;
+}
 // Smallest over largest pivot magnitude of a factored m x m block: a cheap stand-in for
 // the reciprocal of its condition number (1 for a perfectly balanced block).
 template <class T>

@@ -34,8 +34,10 @@ namespace {
 #ifndef VB_ILUT_STEPCAP
 #define VB_ILUT_STEPCAP 8
 #endif
+// at least four resident wavefronts per SIMD (at most 128 registers per lane), so that the
+// 1024 workgroups of a launch are resident together
 #ifndef VB_ILUT_MINWAVES
-#define VB_ILUT_MINWAVES 1
+#define VB_ILUT_MINWAVES 4
 #endif
 constexpr int kIlutThreads = VB_ILUT_THREADS;
 static_assert(kIlutThreads % 64 == 0, "whole wavefronts");
@@ -237,6 +239,53 @@ __device__ inline bool mult_solve_drop(int m, int mk, const T *lu, const int *pi
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     return drop_contig<T>(m, mk, M, t);
 }
+// In-place exclusive prefix sums of a[0..n) (LDS) by the whole workgroup; returns the total
+// to every thread.  Each thread sums a contiguous run of entries, the run sums are scanned
+// within each wavefront and across the wavefronts (part: one int per wavefront), and the
+// runs are rewritten.  Begins and ends with a barrier.
+__device__ inline int wg_scan_excl(int *a, int n, int *part) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int run = (n + kIlutThreads - 1) / kIlutThreads;
+    const int b = t * run, e = b + run < n ? b + run : n;
+    __syncthreads();
+    int sum = 0;
+    for (int q = b; q < e; ++q) sum += a[q];
+    int inc = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) part[wv] = inc;
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int q = 0; q < kIlutThreads / 64; ++q) {
+        base += q < wv ? part[q] : 0;
+        total += part[q];
+    }
+    int acc = base + inc - sum;
+    for (int q = b; q < e; ++q) {
+        const int v = a[q];
+        a[q] = acc;
+        acc += v;
+    }
+    __syncthreads();
+    return total;
+}
+// The entry of a flat list that holds position q: the last e in [0, n) with pre[e] <= q
+// (pre ascending, pre[0] = 0 <= q; an entry with no values shares its start with the next,
+// so the last such e is the one whose values contain q).
+__device__ inline int flat_entry(const int *pre, int n, int q) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= q) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // Copies a rows x tw tile (row stride ld in global memory) to LDS (row stride tw) with nt
 // threads (t = 0..nt-1).  Each thread issues up to six loads before it stores any, so the
 // loads are in flight together.
@@ -711,37 +760,68 @@ __device__ void ilut_row(
     const int ei = h_find(hkeys, hvals, hmask, i);
     if (ei >= 0)
         for (int e = t; e < m * m; e += kIlutThreads) s_M[e] = w[l_offs[ei] + e];
-    __syncthreads();
-    if (t == 0) {
-        s_lc = s_lw = s_uc = s_uw = 0;
-        if (ei < 0) {
-            dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, i);
-            for (int q = 0; q < m * m; ++q) s_M[q] = T(0);
-            for (int q = 0; q < m; ++q) s_piv[q] = q;
-        } else if (!dev_gepp<T>(m, s_M, s_piv)) {
-            dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, i);
-            for (int q = 0; q < m; ++q) s_piv[q] = q;
-        } else {
-            dev_count_illcond<T>(m, s_M, min_ratio, err);
-        }
+    // per entry: block width, and the value count of the upper blocks (tested below)
+    for (int e = t; e < s_nb; e += kIlutThreads) {
+        const int K = l_cols[e];
+        const int nK = rb[K + 1] - rb[K];
+        s_un[e] = nK;
+        s_uoff[e] = K > i ? m * nK : 0;
     }
     __syncthreads();
+    if (t < 64) {
+        // the pivot block, factored by wavefront 0
+        const bool ok = ei >= 0 && wave_gepp<T>(m, s_M, s_piv, t);
+        if (t == 0) {
+            s_lc = s_lw = s_uc = s_uw = 0;
+            if (!ok) {
+                dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, i);
+                if (ei < 0)
+                    for (int q = 0; q < m * m; ++q) s_M[q] = T(0);
+                for (int q = 0; q < m; ++q) s_piv[q] = q;
+            } else {
+                dev_count_illcond<T>(m, s_M, min_ratio, err);
+            }
+        }
+    }
+    // offsets of the upper blocks in one flat list; when they fit, they are staged in LDS in
+    // one round of loads and tested there
+    const int tu = wg_scan_excl(s_uoff, s_nb, s_wmin);
+    const bool ustaged = tu <= lds.ustage;
+    if (ustaged) {
+        for (int q0 = 0; q0 < tu; q0 += 4 * kIlutThreads) {
+            T v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * kIlutThreads + t;
+                v[u] = T(0);
+                if (q < tu) {
+                    const int e = flat_entry(s_uoff, s_nb, q);
+                    v[u] = w[l_offs[e] + (q - s_uoff[e])];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * kIlutThreads + t;
+                if (q < tu) s_U[q] = v[u];
+            }
+        }
+    }
     {
         T *d = dl + dl_off[i];
         for (int e = t; e < m * m; e += kIlutThreads) d[e] = s_M[e];
         for (int q = t; q < m; q += kIlutThreads) dl_piv[rb[i] + q] = s_piv[q];
     }
+    __syncthreads();
     for (int e = t; e < s_nb; e += kIlutThreads) {
-        int K = l_cols[e];
-        int nK = rb[K + 1] - rb[K];
+        const int K = l_cols[e];
         if (K < i) l_est[e] = l_est[e] == 1 ? 3 : 0;
-        else if (K > i) l_est[e] = drop_contig<T>(m, nK, w + l_offs[e], droptol) ? 0 : 4;
+        else if (K > i)
+            l_est[e] = drop_contig<T>(m, s_un[e], ustaged ? s_U + s_uoff[e] : w + l_offs[e], droptol) ? 0 : 4;
         else l_est[e] = 0;
     }
     __syncthreads();
     for (int e = t; e < s_nb; e += kIlutThreads) {
-        int K = l_cols[e];
-        int nK = rb[K + 1] - rb[K];
+        const int nK = s_un[e];
         if (l_est[e] == 3) { atomicAdd(&s_lc, 1); atomicAdd(&s_lw, nK); }
         if (l_est[e] == 4) { atomicAdd(&s_uc, 1); atomicAdd(&s_uw, nK); }
     }
@@ -759,31 +839,59 @@ __device__ void ilut_row(
     }
     __syncthreads();
     if (s_stop) return;
-    // output position = rank by block column; panel offset = widths of smaller columns
+    // output position = rank by block column; panel offset = widths of smaller columns; the
+    // kept blocks' value counts give the flat list the copy below walks
     for (int e = t; e < s_nb; e += kIlutThreads) {
-        int st = l_est[e];
-        if (st != 3 && st != 4) continue;
-        int K = l_cols[e];
-        int rank = 0, off = 0;
-        for (int f = 0; f < s_nb; ++f) {
-            if (l_est[f] == st && l_cols[f] < K) {
-                ++rank;
-                off += rb[l_cols[f] + 1] - rb[l_cols[f]];
+        const int st = l_est[e];
+        int cnt = 0;
+        if (st == 3 || st == 4) {
+            const int K = l_cols[e];
+            int rank = 0, off = 0;
+            for (int f = 0; f < s_nb; ++f) {
+                if (l_est[f] == st && l_cols[f] < K) {
+                    ++rank;
+                    off += s_un[f];
+                }
+            }
+            if (st == 3) {
+                lci[s_lb + rank] = K;
+                lco[s_lb + rank] = off;
+            } else {
+                uci[s_ub + rank] = K;
+                uco[s_ub + rank] = off;
+            }
+            s_ucol[e] = off;
+            cnt = m * s_un[e];
+        }
+        s_uc0[e] = cnt;
+    }
+    const int tc = wg_scan_excl(s_uc0, s_nb, s_wmin);
+    // the kept blocks' values to the panels, all threads over the flat list, four values
+    // per thread loaded before any is stored
+    for (int q0 = 0; q0 < tc; q0 += 4 * kIlutThreads) {
+        T v[4];
+        T *dst[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u * kIlutThreads + t;
+            v[u] = T(0);
+            dst[u] = nullptr;
+            if (q < tc) {
+                const int e = flat_entry(s_uc0, s_nb, q);
+                const int local = q - s_uc0[e], nK = s_un[e];
+                const int r = local / nK, c = local - r * nK;
+                if (l_est[e] == 3) {
+                    dst[u] = lv + s_lv + (int64_t)r * s_lw + s_ucol[e] + c;
+                    v[u] = w[l_offs[e] + local];
+                } else {
+                    dst[u] = uv + s_uv + (int64_t)r * s_uw + s_ucol[e] + c;
+                    v[u] = ustaged ? s_U[s_uoff[e] + local] : w[l_offs[e] + local];
+                }
             }
         }
-        int nK = rb[K + 1] - rb[K];
-        const T *src = w + l_offs[e];
-        if (st == 3) {
-            lci[s_lb + rank] = K;
-            lco[s_lb + rank] = off;
-            for (int r = 0; r < m; ++r)
-                for (int c = 0; c < nK; ++c) lv[s_lv + (int64_t)r * s_lw + off + c] = src[r * nK + c];
-        } else {
-            uci[s_ub + rank] = K;
-            uco[s_ub + rank] = off;
-            for (int r = 0; r < m; ++r)
-                for (int c = 0; c < nK; ++c) uv[s_uv + (int64_t)r * s_uw + off + c] = src[r * nK + c];
-        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (dst[u]) *dst[u] = v[u];
     }
     if (t == 0) {
         rec[i] = IlutRowRec{s_lb, s_lv, s_ub, s_uv, s_lc, s_lw, s_uc, s_uw, dl_off[i], rb[i], m};

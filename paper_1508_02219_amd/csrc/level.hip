@@ -39,20 +39,23 @@ __global__ void k_rowmax(int64_t n, const int *rowblk, const int *rb, const int6
     if (row < n && lane == 0) s1[row] = mx > 0.0 ? 1.0 / mx : 1.0;
 }
 
+// Column maxima of |s1_r a_rj|: kTG lanes per block row stride over its panel columns, each
+// lane takes the maximum over the block row's scalar rows itself and issues one atomic per
+// column of the block row (the maximum does not depend on the order of the rows).
 template <class T>
-__global__ void k_colmax(int64_t n, const int *rowblk, const int *rb, const int64_t *wp, const int64_t *vp,
-                         const int *sc, const T *v, const double *s1, unsigned long long *cmax) {
+__global__ void k_colmax(int p, const int *rb, const int64_t *wp, const int64_t *vp, const int *sc, const T *v,
+                         const double *s1, unsigned long long *cmax) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t row = gid / kTG;
+    int64_t I = gid / kTG;
     int lane = (int)(gid % kTG);
-    if (row >= n) return;
-    int I = rowblk[row];
-    int64_t W = wp[I + 1] - wp[I];
-    const T *a = v + vp[I] + (row - rb[I]) * W;
+    if (I >= p) return;
+    const int r0 = rb[I], m = rb[I + 1] - r0;
+    const int64_t W = wp[I + 1] - wp[I];
+    const T *a = v + vp[I];
     const int *c = sc + wp[I];
-    double sr = s1[row];
     for (int64_t j = lane; j < W; j += kTG) {
-        double x = fabs(sr * (double)a[j]);
+        double x = 0.0;
+        for (int r = 0; r < m; ++r) x = fmax(x, fabs(s1[r0 + r] * (double)a[(int64_t)r * W + j]));
         if (x > 0.0) atomicMax(&cmax[c[j]], dbits(x));
     }
 }
@@ -128,17 +131,9 @@ __global__ void k_block_sq(int nis, const int *is_list, const int *rb, int64_t *
     sq[i] = (int64_t)m * m;
 }
 
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // Pivot-block GEPP, one wavefront per block of the independent set (four per workgroup),
-// the block staged in LDS.  The pivot search is a wavefront reduction that picks the row
-// the sequential scan of dev_gepp picks (the first row of largest modulus, the diagonal
-// kept on ties; a NaN never wins and a NaN diagonal keeps its row), and every element
-// update is dev_gepp's, so the factors are the same bit for bit.
+// the block staged in LDS and factored by wave_gepp (the same factors as dev_gepp, bit for
+// bit).
 template <class T>
 __global__ void __launch_bounds__(256) k_gepp(int nis, const int *is_list, const int *rb, const int64_t *rp,
                                               const int *ci, const int *co, const int64_t *wp, const int64_t *vp,
@@ -162,46 +157,9 @@ __global__ void __launch_bounds__(256) k_gepp(int nis, const int *is_list, const
     const T *src = v + vp[I] + co[k0];
     for (int e = lane; e < m * m; e += 64) a[e] = src[(int64_t)(e / m) * W + (e % m)];
     wave_sync();
-    for (int k = 0; k < m; ++k) {
-        const T akk = fabs(a[k * m + k]);
-        // largest modulus below the diagonal, the first row on ties (NaN as -1)
-        T vv = T(-1);
-        int rr = m;
-        if (lane > k && lane < m) {
-            const T x = fabs(a[lane * m + k]);
-            vv = x != x ? T(-1) : x;
-            rr = lane;
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const T ov = __shfl_xor(vv, off, 64);
-            const int orr = __shfl_xor(rr, off, 64);
-            if (ov > vv || (ov == vv && orr < rr)) {
-                vv = ov;
-                rr = orr;
-            }
-        }
-        const int pr = (akk == akk && vv > akk) ? rr : k;
-        const T amax = pr == k ? akk : vv;
-        if (lane == 0) pv[k] = pr;
-        if (amax == T(0)) {
-            if (lane == 0) dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, I);
-            return;
-        }
-        if (pr != k && lane < m) {
-            const T t = a[k * m + lane];
-            a[k * m + lane] = a[pr * m + lane];
-            a[pr * m + lane] = t;
-        }
-        wave_sync();
-        if (lane > k && lane < m) a[lane * m + k] = a[lane * m + k] / a[k * m + k];
-        wave_sync();
-        const int rest = m - k - 1;
-        for (int e = lane; e < rest * rest; e += 64) {
-            const int r = k + 1 + e / rest, c = k + 1 + e % rest;
-            a[r * m + c] = a[r * m + c] - a[r * m + k] * a[k * m + c];
-        }
-        wave_sync();
+    if (!wave_gepp<T>(m, a, pv, lane)) {
+        if (lane == 0) dev_set_error(err, VBARMS_ERR_SINGULAR, lvl, I);
+        return;
     }
     T *d = dlu + dlu_off[i];
     for (int e = lane; e < m * m; e += 64) d[e] = a[e];
@@ -810,8 +768,11 @@ void factor_level(Level<T> &L, Panel<T> &&Ain, int lvl, double droptol, int drop
         unsigned g = grid_for((int64_t)n * kTG, 256);
         k_rowmax<T><<<g, 256, 0, s>>>(n, A.rowblk.p, A.rb.p, A.wp.p, A.vp.p, A.v.p, L.s1.p);
         VB_LAUNCH_CHECK();
-        k_colmax<T><<<g, 256, 0, s>>>(n, A.rowblk.p, A.rb.p, A.wp.p, A.vp.p, A.sc.p, A.v.p, L.s1.p, cm.p);
-        VB_LAUNCH_CHECK();
+        if (p > 0) {
+            k_colmax<T><<<grid_for((int64_t)p * kTG, 256), 256, 0, s>>>(p, A.rb.p, A.wp.p, A.vp.p, A.sc.p, A.v.p,
+                                                                       L.s1.p, cm.p);
+            VB_LAUNCH_CHECK();
+        }
         k_s2<<<grid_for(n, 256), 256, 0, s>>>(n, cm.p, L.s2.p);
         VB_LAUNCH_CHECK();
         // scaled copy shares the layout

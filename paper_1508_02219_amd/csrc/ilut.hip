@@ -912,24 +912,16 @@ __device__ void ilut_row(
 constexpr int kGatherThreads = 256;
 constexpr int kGatherItems = 4;
 
-__global__ void __launch_bounds__(kGatherThreads) k_ilut_gather(int p, const IlutWait *wait_in, const int *cnt_wait_in,
+__global__ void __launch_bounds__(kGatherThreads) k_ilut_gather(const IlutWait *wait_in, const int *cnt_wait_in,
                                                                 const int *done, int *ready, int *cnt_ready,
                                                                 IlutWait *wait_out, int *cnt_wait_out,
                                                                 int *min_ready) {
     constexpr int NW = kGatherThreads / 64;
     __shared__ int s_tr[NW], s_tw[NW], s_br[NW], s_bw[NW], s_mn[NW];
+    const int n = *cnt_wait_in;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     constexpr int tile = kGatherThreads * kGatherItems;
-    // the first tile's entries are loaded together with the count (any index below p lies
-    // inside the list; entries at or beyond the count are ignored)
-    IlutWait pre[kGatherItems];
-#pragma unroll
-    for (int u = 0; u < kGatherItems; ++u) {
-        const int e = blockIdx.x * tile + u * kGatherThreads + t;
-        if (e < p) pre[u] = wait_in[e];
-    }
-    const int n = *cnt_wait_in;
     for (int b0 = blockIdx.x * tile; b0 < n; b0 += gridDim.x * tile) {
         IlutWait ent[kGatherItems];
         bool has[kGatherItems], rdy[kGatherItems];
@@ -938,7 +930,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_ilut_gather(int p, const Ilu
             const int e = b0 + u * kGatherThreads + t;
             has[u] = e < n;
             if (has[u]) {
-                ent[u] = b0 == (int)blockIdx.x * tile ? pre[u] : wait_in[e];
+                ent[u] = wait_in[e];
             } else {
                 ent[u].row = -1;
 #pragma unroll
@@ -1337,7 +1329,7 @@ void factor_last(LastLevel<T> &last, double droptol, double min_ratio, int lvl, 
                 ++launch;
                 const IlutWait *w_in = waits.p + (size_t)(launch & 1) * p;
                 IlutWait *w_out = waits.p + (size_t)((launch + 1) & 1) * p;
-                k_ilut_gather<<<kGatherBlocks, kGatherThreads, 0, s>>>(p, w_in, cw + launch % 3, done.p, ready.p,
+                k_ilut_gather<<<kGatherBlocks, kGatherThreads, 0, s>>>(w_in, cw + launch % 3, done.p, ready.p,
                                                             cr + launch % 2, w_out, cw + (launch + 1) % 3,
                                                             mr + launch % 2);
                 VB_LAUNCH_CHECK();
